@@ -1,0 +1,226 @@
+"""Benchmark: the D2Q9 finite-volume time step on one MI355X.
+
+Headline workload: periodic Taylor-Green vortex on a 4096 x 4096 uniform mesh,
+DUGKS, FP64 (the only single-GPU case whose 2.4 GB of traffic per step exceeds
+the 256 MB Infinity Cache, so that HBM bandwidth is what is measured).  One
+"step" is one full time step of the path (moments, equilibrium and collision
+transforms, reconstruction and half-step trace at every face, wall / ghost
+handling, interface moments and back-transform, flux divergence and update),
+with the FP64 check reduction (totals + non-finite flag) every `--check-every`
+steps inside the timed region.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line (rank 0); see the design doc for the fields.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+BYTES = {"f64": 144, "f32": 72, "bf16": 36, "f16": 36}   # algorithmic bytes per cell-step (9 reads + 9 writes)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--n", type=int, default=4096, help="mesh side of the headline workload")
+    p.add_argument("--check-every", type=int, default=100)
+    p.add_argument("--no-variants", action="store_true")
+    p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--cpu-steps", type=int, default=3)
+    p.add_argument("--only", default="", help="comma list of variant names to run")
+    p.add_argument("--tile", default="", help="rows,waves_per_block for every run (skips the autotuner)")
+    p.add_argument("--copy-probe-mb", type=int, default=0,
+                   help="also run a plain device copy of this many MiB (calibrates HBM byte counters)")
+    return p.parse_args()
+
+
+def timed_steps(ctx, scheme, steps, warmup, stream):
+    """Warm up, then time `steps` steps with HIP events on the library's stream."""
+    import torch
+    ctx.step(scheme, warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    ctx.step(scheme, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1), wall * 1e3
+
+
+def run_single(name, w, scheme, compute, storage, steps, warmup, check_every, stream, tile=None):
+    from paper_1511_00242_amd import lbfv as L
+    ctx = L.Context(w.xf, w.yf, w.tau, w.dt, rt=w.rt, bcs=w.bcs, compute=compute, storage=storage,
+                    check_every=check_every, stream=stream.cuda_stream)
+    ctx.bind_torch_buffers()
+    ctx.init_equilibrium(w.rho, w.ux, w.uy)
+    if tile:
+        ctx.set_tile(*tile)
+    else:
+        ctx.autotune(scheme, 10, os.environ.get("LBFV_TUNE_CACHE"))
+    ms, wall_ms = timed_steps(ctx, scheme, steps, warmup, stream)
+    rows, wpb = ctx.get_tile()
+    tot = ctx.totals()                       # also re-checks for non-finite values
+    ctx.close()
+    cells = w.nx * w.ny
+    per = ms / steps
+    return dict(name=name, ms_per_step=per, mlups=cells / (per * 1e-3) / 1e6, wall_ms=wall_ms,
+                tile=[rows, wpb], mass=tot[0])
+
+
+def run_batch(steps, warmup, stream):
+    import torch
+    from paper_1511_00242_amd import inputs as I
+    from paper_1511_00242_amd import lbfv as L
+    cases = I.batch_cases()
+    b = L.Batch(cases, stream=stream.cuda_stream)
+    for i, w in enumerate(cases):
+        b.init_equilibrium(i, w.rho, w.ux, w.uy)
+    cells, items = b.info()
+    b.step(L.LBFV_DUGKS, warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    b.step(L.LBFV_DUGKS, steps)             # `steps` is a multiple of the graph length
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    b.close()
+    # the same cases stepped one at a time with the plain FP64 kernel
+    t_seq = 0.0
+    for w in cases:
+        ctx = L.Context(w.xf, w.yf, w.tau, w.dt, bcs=w.bcs, check_every=0, stream=stream.cuda_stream)
+        ctx.init_equilibrium(w.rho, w.ux, w.uy)
+        ctx.dugks_step(4)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        ctx.dugks_step(32)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_seq += e0.elapsed_time(e1) / 32
+        ctx.close()
+    return dict(name="batch96_dugks_fp32dev", cases=len(cases), cells=cells, work_items=items,
+                ms_per_step=ms, mlups=cells / (ms * 1e-3) / 1e6, gbs=cells * BYTES["f32"] / (ms * 1e-3) / 1e9,
+                seq_fp64_ms_per_step=t_seq, speedup_vs_seq_fp64=t_seq / ms)
+
+
+def cpu_baseline(n, steps):
+    """The FP64 oracle on the host's cores over a bounded sample of the workload."""
+    from oracle import oracle as O
+    from paper_1511_00242_amd import inputs as I
+    threads = min(16, os.cpu_count() or 1)
+    w = I.taylor_green(n)
+    c = O.Case(w.xf, w.yf, w.rt, w.tau, w.dt, w.bcs, threads=threads)
+    f = c.init_equilibrium(w.rho, w.ux, w.uy)
+    t0 = time.perf_counter()
+    c.run(f, O.DUGKS, steps)
+    el = time.perf_counter() - t0
+    return {"value": n * n * steps / el / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"taylor_green {n}x{n}, {steps} DUGKS steps, FP64 ({el:.1f} s)"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_1511_00242_amd import inputs as I
+    from paper_1511_00242_amd import lbfv as L
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    steps = max(2, a.steps)
+    tile = tuple(int(x) for x in a.tile.split(",")) if a.tile else None
+    if a.copy_probe_mb:
+        n = a.copy_probe_mb * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy probe: 3 copies of {a.copy_probe_mb} MiB", file=sys.stderr, flush=True)
+        del src, dst
+
+    w = I.taylor_green(a.n)
+    head = run_single("dugks_fp64", w, L.LBFV_DUGKS, L.LBFV_FP64, L.LBFV_STORE_NATIVE, steps, a.warmup,
+                      a.check_every, stream, tile)
+    print(f"[bench] dugks fp64 {a.n}^2: {head['ms_per_step']:.4f} ms/step {head['mlups']:.0f} MLUPS",
+          file=sys.stderr, flush=True)
+    cells = w.nx * w.ny
+    gbs = cells * BYTES["f64"] / (head["ms_per_step"] * 1e-3) / 1e9
+
+    variants = {}
+    if not a.no_variants:
+        only = set(x for x in a.only.split(",") if x)
+        specs = [("bkg_fp64", L.LBFV_BKG, L.LBFV_FP64, L.LBFV_STORE_NATIVE, "f64"),
+                 ("dugks_fp32dev", L.LBFV_DUGKS, L.LBFV_FP32, L.LBFV_STORE_DEV_FP32, "f32"),
+                 ("bkg_fp32dev", L.LBFV_BKG, L.LBFV_FP32, L.LBFV_STORE_DEV_FP32, "f32"),
+                 ("dugks_bf16dev", L.LBFV_DUGKS, L.LBFV_FP32, L.LBFV_STORE_DEV_BF16, "bf16"),
+                 ("dugks_fp16dev", L.LBFV_DUGKS, L.LBFV_FP32, L.LBFV_STORE_DEV_FP16, "f16")]
+        for name, sch, comp, sto, dt in specs:
+            if only and name not in only:
+                continue
+            r = run_single(name, w, sch, comp, sto, steps, a.warmup, a.check_every, stream, tile)
+            r["gbs"] = cells * BYTES[dt] / (r["ms_per_step"] * 1e-3) / 1e9
+            r["hbm_frac"] = r["gbs"] / HBM_PEAK_GBS
+            r["speedup_vs_dugks_fp64"] = head["ms_per_step"] / r["ms_per_step"]
+            variants[name] = r
+            print(f"[bench] {name}: {r['ms_per_step']:.4f} ms/step {r['mlups']:.0f} MLUPS", file=sys.stderr,
+                  flush=True)
+        if not only or "batch" in only:
+            r = run_batch(100, 100, stream)
+            variants["batch"] = r
+            print(f"[bench] batch: {r['ms_per_step']:.4f} ms/step {r['mlups']:.0f} MLUPS", file=sys.stderr,
+                  flush=True)
+        if "bkg_fp64" in variants:
+            variants["dugks_over_bkg_cost_fp64"] = head["ms_per_step"] / variants["bkg_fp64"]["ms_per_step"]
+
+    out = {
+        "metric": "MLUPS and % HBM peak per step (DUGKS, BKG; FP64 vs FP32/batched)",
+        "value": head["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": a.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (analytic Taylor-Green field, no dataset)",
+        "config": {"workload": f"taylor_green_{a.n}x{a.n}_dugks_fp64", "nx": a.n, "ny": a.n,
+                   "scheme": "dugks", "precision": "fp64", "boundary": "periodic",
+                   "check_every": a.check_every, "tile_rows_waves": head["tile"],
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "lbfv::step_kernel<double,double,DUGKS>",
+                     "bytes_per_cell_step": BYTES["f64"]},
+        "variants": variants,
+        "context": {"paper_cpu_mlups_64x64": {"dugks": 2.08, "bkg": 3.90,
+                                              "hardware": "Xeon E5-2670v3 (paper Sec. 3.1)"}},
+    }
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(a.n, a.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,187 @@
+/*
+ * lbfv.h -- C ABI of liblbfv: MI355X (gfx950) D2Q9 finite-volume time steps of
+ * the discrete velocity Boltzmann-BGK equation, for the two schemes compared by
+ * Zhu, Wang & Guo (arXiv 1511.00242):
+ *
+ *   DUGKS (Sec. 2.2): the tracked f~ = f - (dt/2) Omega is advanced by
+ *     f~^{n+1} = f~+ - (dt/|V|) sum_faces (xi.n) f^{n+1/2} S, with the face value
+ *     obtained from the half-step characteristic solution: f-bar+ traced back by
+ *     h = dt/2 with a linear reconstruction, face moments, face equilibrium, and the
+ *     trapezoid back-transform (Eqs. eq_update, eq_flux, eq_char, eq_trans_2).
+ *   BKG (Sec. 2.3): the same update with the face value f~+(x_b - h xi), i.e. the
+ *     collision step of the standard LBM followed by Lax-Wendroff streaming in
+ *     finite-volume form (Eqs. bkg_collision, lwfv, bkg_fb, bkg_fv, f_left).
+ *
+ * Both schemes track the same variable f~, so a state may be advanced by either.
+ * Boundary conditions (Sec. 2.5, Sec. 3.3): periodic, half-way bounce-back of a
+ * moving no-slip wall with ghost cells by linear extrapolation, equilibrium
+ * (free-stream) inflow, zero- or first-order extrapolation outflow.
+ *
+ * Conventions for every function:
+ *   - returns LBFV_OK (0) or a negative lbfv_status; nothing is thrown across the ABI;
+ *   - pointers are host pointers unless named dev_*; input arrays are copied during
+ *     the call, output arrays are caller-allocated;
+ *   - host fields are FP64, row-major [ny][nx] (x fastest); distributions are SoA
+ *     [9][ny][nx] in the direction order of Sec. 2.1:
+ *       0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1) 7:(-1,-1) 8:(1,-1)
+ *     times c = sqrt(3 RT);
+ *   - one context is not thread-safe; distinct contexts are independent;
+ *   - stepping is asynchronous on the context's HIP stream; observables
+ *     (moments, totals, residual, get_f) synchronise that stream.
+ */
+#ifndef LBFV_H
+#define LBFV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBFV_OK = 0,
+    LBFV_EINVAL = -1,        /* bad argument (NULL, size, ordering, unsupported combination) */
+    LBFV_ESTATE = -2,        /* call not valid in the current state (unset side, no initial state) */
+    LBFV_ENOMEM = -3,        /* device or host allocation failed */
+    LBFV_EHIP = -4,          /* a HIP runtime call failed (see lbfv_last_error) */
+    LBFV_EUNSTABLE = -5,     /* a non-finite value was found at a check */
+    LBFV_EUNSUPPORTED = -6   /* valid request that this build does not provide */
+} lbfv_status;
+
+enum { LBFV_DUGKS = 0, LBFV_BKG = 1 };
+enum { LBFV_WEST = 0, LBFV_EAST = 1, LBFV_SOUTH = 2, LBFV_NORTH = 3 };
+enum { LBFV_X = 0, LBFV_Y = 1 };
+enum { LBFV_FP64 = 0, LBFV_FP32 = 1 };
+enum { LBFV_STORE_NATIVE = 0, LBFV_STORE_DEV_FP32 = 1, LBFV_STORE_DEV_BF16 = 2, LBFV_STORE_DEV_FP16 = 3 };
+
+typedef struct lbfv_ctx lbfv_ctx;
+typedef struct lbfv_batch lbfv_batch;
+
+/* Structured mesh (Sec. 2.2 control volumes): xf[nx+1], yf[ny+1] strictly increasing
+ * face coordinates, uniform or stretched.  Copied at create. */
+typedef struct {
+    int32_t nx, ny;
+    const double *xf, *yf;
+} lbfv_mesh;
+
+/* Velocity set (Sec. 2.1): q must be 9 (D2Q9); rt = RT = c_s^2 > 0. */
+typedef struct {
+    int32_t q;
+    double rt;
+} lbfv_velset;
+
+/* Options (NULL = defaults: FP64, native storage, rho0 = 1, check_every = 1000,
+ * default stream).
+ *   compute     LBFV_FP64 or LBFV_FP32 arithmetic.
+ *   storage     LBFV_STORE_NATIVE stores f~ in the compute type; LBFV_STORE_DEV_* store
+ *               the deviation f~_a - w_a rho0 as FP32, BF16 or FP16 (the 16-bit forms
+ *               hold (f~_a - w_a rho0)/w_a); DEV_* need FP32 compute.
+ *   rho0        reference density of the deviation storage.
+ *   check_every steps between the FP64 checks (non-finite flag); 0 disables them.
+ *   hip_stream  hipStream_t to run on; NULL = the default stream. */
+typedef struct {
+    int32_t compute;
+    int32_t storage;
+    double rho0;
+    int32_t check_every;
+    void *hip_stream;
+} lbfv_opts;
+
+/* Create a context for one mesh.  tau: relaxation time (nu = tau RT, Eq. nu_tau);
+ * dt: time step.  CFL >= 1 is allowed (stability is the caller's choice).
+ * EINVAL: NULL ctx or mesh, nx or ny < 2, non-increasing faces, q != 9, rt <= 0,
+ * tau <= 0, dt <= 0, 16-bit or deviation storage with FP64 compute.  Device buffers
+ * are allocated on first use unless lbfv_bind_buffers supplies them. */
+int lbfv_create(const lbfv_mesh *mesh, const lbfv_velset *vel, double tau, double dt,
+                const lbfv_opts *opts, lbfv_ctx **ctx);
+int lbfv_destroy(lbfv_ctx *ctx);
+
+/* Eq. eq:cfl: dt = cfl * dx / (sqrt(6) c_s), dx = smallest cell size of the mesh. */
+int lbfv_dt_from_cfl(const lbfv_mesh *mesh, double rt, double cfl, double *dt);
+
+/* Boundary setters.  All four sides must be set before the first step (else ESTATE);
+ * a periodic axis is set as a whole.  Changing a side is allowed between steps. */
+int lbfv_set_periodic(lbfv_ctx *ctx, int axis);
+/* Half-way bounce-back wall moving with (uwx, uwy) (Sec. 2.5); ghost cells by linear
+ * extrapolation of f-bar+ (DUGKS) or f~+ (BKG) to the mirrored centre. */
+int lbfv_set_wall(lbfv_ctx *ctx, int side, double uwx, double uwy);
+/* Free stream / inflow: ghost cells hold feq(rho, u). */
+int lbfv_set_inflow_eq(lbfv_ctx *ctx, int side, double rho, double ux, double uy);
+/* Outflow: ghost cells copy the adjacent cell (order 0) or extrapolate linearly (order 1). */
+int lbfv_set_outflow_extrap(lbfv_ctx *ctx, int side, int order);
+
+/* State.  f~ of an equilibrium state is feq (Omega(feq) = 0). */
+int lbfv_init_equilibrium(lbfv_ctx *ctx, const double *rho, const double *ux, const double *uy);
+int lbfv_set_f(lbfv_ctx *ctx, const double *f);   /* f~, [9][ny][nx] FP64 */
+int lbfv_get_f(lbfv_ctx *ctx, double *f);         /* f~, [9][ny][nx] FP64 */
+/* Use caller-owned device buffers (e.g. PyTorch tensors) for the two state buffers;
+ * each must hold lbfv_required_bytes and outlive the context.  The current state is
+ * not carried over (set it again afterwards). */
+int lbfv_bind_buffers(lbfv_ctx *ctx, void *dev_a, void *dev_b, size_t bytes);
+int lbfv_required_bytes(const lbfv_ctx *ctx, size_t *bytes_per_buffer);
+
+/* Advance nsteps time steps; asynchronous on the context stream.  Returns EUNSTABLE
+ * if an earlier check found a non-finite value, ESTATE if a side is unset or no state
+ * has been set. */
+int dugks_step(lbfv_ctx *ctx, int32_t nsteps);
+int bkg_step(lbfv_ctx *ctx, int32_t nsteps);
+
+/* Observables, FP64, synchronising the stream.
+ * lbfv_moments: rho = sum f~, rho u = sum xi f~ (Sec. 2.2, Eq. macro_var).
+ * lbfv_totals:  out[0] = sum rho |V|, out[1..2] = sum rho u |V| (fixed reduction order).
+ * lbfv_residual: ||u - u_prev||_2 / ||u||_2 over both components and all cells, where
+ *               u_prev is the velocity at the previous lbfv_residual call (1.0 on the
+ *               first call). */
+int lbfv_moments(lbfv_ctx *ctx, double *rho, double *ux, double *uy);
+int lbfv_totals(lbfv_ctx *ctx, double out[3]);
+int lbfv_residual(lbfv_ctx *ctx, double *r);
+
+/* Execution shape of the step kernel: rows of the row block one wavefront marches
+ * through, and wavefronts per workgroup (1, 2 or 4).  0 keeps the current value. */
+int lbfv_set_tile(lbfv_ctx *ctx, int32_t rows, int32_t waves_per_block);
+int lbfv_get_tile(const lbfv_ctx *ctx, int32_t *rows, int32_t *waves_per_block);
+/* Autotuner: times the candidate shapes for `scheme` on this context (the state is
+ * saved and restored), keeps the fastest, and records it in a cache file keyed by
+ * (gfx arch, scheme, precision, storage, mesh size class).  cache_path NULL: the
+ * environment variable LBFV_TUNE_CACHE, else no file.  A cached entry is used
+ * without timing.  best_ms (nullable) receives the time per step of the choice. */
+int lbfv_autotune(lbfv_ctx *ctx, int scheme, int32_t trial_steps, const char *cache_path,
+                  double *best_ms);
+
+const char *lbfv_strerror(int status);
+const char *lbfv_last_error(const lbfv_ctx *ctx);   /* ctx NULL: last error of this thread */
+
+/* ------------------------------------------------------------------------------
+ * Batched form: many independent cases of uneven size, Reynolds number and boundary
+ * type advanced together.  One persistent kernel launch per time step walks a flat
+ * list of (case, strip, row block) items; lbfv_batch_step replays a HIP graph of
+ * K such launches.  Compute / storage follow opts (FP32 deviation storage is the
+ * intended use).  bc_kind per side: 0 periodic, 1 wall (bc_val = uwx, uwy),
+ * 2 inflow (rho, ux, uy), 3 outflow (order). */
+typedef struct {
+    lbfv_mesh mesh;
+    double tau, dt;
+    int32_t bc_kind[4];
+    double bc_val[4][3];
+} lbfv_case;
+
+int lbfv_batch_create(int32_t n, const lbfv_case *cases, const lbfv_velset *vel,
+                      const lbfv_opts *opts, lbfv_batch **batch);
+int lbfv_batch_init_equilibrium(lbfv_batch *b, int32_t case_id, const double *rho,
+                                const double *ux, const double *uy);
+int lbfv_batch_set_f(lbfv_batch *b, int32_t case_id, const double *f);
+int lbfv_batch_get_f(lbfv_batch *b, int32_t case_id, double *f);
+/* Advance every case by nsteps (scheme LBFV_DUGKS or LBFV_BKG); whole multiples of
+ * the graph length K run as graph replays, the rest as single launches. */
+int lbfv_batch_step(lbfv_batch *b, int scheme, int32_t nsteps);
+int lbfv_batch_moments(lbfv_batch *b, int32_t case_id, double *rho, double *ux, double *uy);
+/* Graph length K (default 100) and rows per row block of the work list. */
+int lbfv_batch_set_shape(lbfv_batch *b, int32_t graph_steps, int32_t rows);
+int lbfv_batch_info(const lbfv_batch *b, int64_t *total_cells, int32_t *work_items);
+int lbfv_batch_destroy(lbfv_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBFV_H */

@@ -1,0 +1,161 @@
+// aux_kernels.hpp -- state conversion, observables and FP64 reductions for liblbfv.
+// Not on the per-step path except the periodic check reduction.
+#pragma once
+#include "kernels.hpp"
+
+namespace lbfv {
+
+// Flat cell index -> stored element offset of direction 0.
+template <typename T>
+__device__ __forceinline__ int64_t cell_offset(const StepParams<T> &P, int64_t k) {
+    const int64_t j = k / P.nx, i = k - j * P.nx;
+    return j * P.pitch + i;
+}
+
+// f~ of an equilibrium state (Omega(feq) = 0): x_a = w_a (rho - rho0 + rho P_a(u / c)),
+// evaluated in FP64 and rounded once to the stored type.
+template <typename T, typename S>
+__global__ void init_eq_kernel(StepParams<T> P, int parity, const double *rho, const double *ux,
+                               const double *uy, double inv_c, double rho0) {
+    const int64_t n = (int64_t)P.nx * P.ny;
+    S *dst = (S *)P.buf[parity];
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const double r = rho[k], u = ux[k] * inv_c, v = uy[k] * inv_c;
+        const double usq15 = 1.5 * (u * u + v * v);
+        S *p = dst + cell_offset(P, k);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            const double x = dfeq<double>(a, r - rho0, r, r * u, r * v, u, v, usq15);
+            p[a * P.plane] = Storage<S>::store((T)x, a);
+        }
+    }
+}
+
+// host-layout FP64 f~ [9][ny][nx] -> stored deviations
+template <typename T, typename S>
+__global__ void set_f_kernel(StepParams<T> P, int parity, const double *f, double rho0) {
+    const int64_t n = (int64_t)P.nx * P.ny;
+    S *dst = (S *)P.buf[parity];
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        S *p = dst + cell_offset(P, k);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            p[a * P.plane] = Storage<S>::store((T)(f[a * n + k] - wgt(a) * rho0), a);
+        }
+    }
+}
+
+template <typename T, typename S>
+__global__ void get_f_kernel(StepParams<T> P, int parity, double *f, double rho0) {
+    const int64_t n = (int64_t)P.nx * P.ny;
+    const S *src = (const S *)P.buf[parity];
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const S *p = src + cell_offset(P, k);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            f[a * n + k] = (double)Storage<S>::load(p[a * P.plane], a) + wgt(a) * rho0;
+        }
+    }
+}
+
+// Moments in FP64 from the stored values (Sec. 2.2, Eq. macro_var).
+template <typename T, typename S>
+__device__ __forceinline__ bool cell_moments64(const StepParams<T> &P, const S *src, int64_t k, double rho0,
+                                               double c, double &rho, double &ux, double &uy) {
+    const S *p = src + cell_offset(P, k);
+    double x[9];
+    bool finite = true;
+    #pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        x[a] = (double)Storage<S>::load(p[a * P.plane], a);
+        finite = finite && isfinite(x[a]);
+    }
+    double d = x[0];
+#pragma unroll
+    for (int a = 1; a < 9; ++a) d += x[a];
+    rho = rho0 + d;
+    ux = c * (x[1] - x[3] + x[5] - x[6] - x[7] + x[8]) / rho;
+    uy = c * (x[2] - x[4] + x[5] + x[6] - x[7] - x[8]) / rho;
+    return finite && isfinite(rho) && isfinite(ux) && isfinite(uy);
+}
+
+template <typename T, typename S>
+__global__ void moments_kernel(StepParams<T> P, int parity, double *rho, double *ux, double *uy, double rho0,
+                               double c) {
+    const int64_t n = (int64_t)P.nx * P.ny;
+    const S *src = (const S *)P.buf[parity];
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        double r, u, v;
+        cell_moments64(P, src, k, rho0, c, r, u, v);
+        rho[k] = r;
+        ux[k] = u;
+        uy[k] = v;
+    }
+}
+
+// Check / observable reduction.  Per block, in FP64 and a fixed order:
+//   [0] sum rho |V|  [1] sum rho u |V|  [2] sum rho v |V|  [3] sum |u - u_prev|^2
+//   [4] sum |u|^2    [5] number of cells with a non-finite value
+// mode bit 1: residual terms (and u_prev := u).
+constexpr int RED_BLOCK = 256;
+constexpr int RED_N = 6;
+
+__device__ __forceinline__ void block_sum(double (&v)[RED_N], double (*sh)[RED_BLOCK], double *out) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < RED_N; ++q) sh[q][t] = v[q];
+    __syncthreads();
+    for (int s = RED_BLOCK / 2; s > 0; s >>= 1) {
+        if (t < s) {
+#pragma unroll
+            for (int q = 0; q < RED_N; ++q) sh[q][t] += sh[q][t + s];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+#pragma unroll
+        for (int q = 0; q < RED_N; ++q) out[q] = sh[q][0];
+    }
+}
+
+template <typename T, typename S>
+__global__ __launch_bounds__(RED_BLOCK) void reduce_kernel(StepParams<T> P, int parity, const double *dxs,
+                                                           const double *dys, double *uprev, int mode,
+                                                           double rho0, double c, double *partial) {
+    __shared__ double sh[RED_N][RED_BLOCK];
+    const int64_t n = (int64_t)P.nx * P.ny;
+    const S *src = (const S *)P.buf[parity];
+    double v[RED_N] = {0, 0, 0, 0, 0, 0};
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        double r, u, w;
+        const bool ok = cell_moments64(P, src, k, rho0, c, r, u, w);
+        if (!ok) {
+            v[5] += 1.0;
+            continue;
+        }
+        const int64_t j = k / P.nx, i = k - j * P.nx;
+        const double vol = dxs[i] * dys[j];
+        v[0] += r * vol;
+        v[1] += r * u * vol;
+        v[2] += r * w * vol;
+        if (mode & 1) {
+            const double du = u - uprev[k], dv = w - uprev[n + k];
+            v[3] += du * du + dv * dv;
+            v[4] += u * u + w * w;
+            uprev[k] = u;
+            uprev[n + k] = w;
+        }
+    }
+    block_sum(v, sh, partial + (int64_t)blockIdx.x * RED_N);
+}
+
+__global__ __launch_bounds__(RED_BLOCK) void reduce_final_kernel(const double *partial, int nblocks, double *out) {
+    __shared__ double sh[RED_N][RED_BLOCK];
+    double v[RED_N] = {0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += RED_BLOCK)
+#pragma unroll
+        for (int q = 0; q < RED_N; ++q) v[q] += partial[(int64_t)b * RED_N + q];
+    block_sum(v, sh, out);
+}
+
+}  // namespace lbfv

@@ -1,0 +1,543 @@
+// kernels.hpp -- gfx950 device code for the D2Q9 finite-volume DUGKS and BKG
+// steps of Zhu, Wang & Guo (arXiv 1511.00242), Sec. 2.2-2.5.
+//
+// Execution model.  One wavefront (64 lanes) owns a strip of 64 consecutive
+// columns: lane l holds column x0-1+l, so lanes 1..62 produce output and lanes
+// 0 and 63 are the x-halo.  The wave marches up its rows (row block [j0, j1))
+// keeping three rows of phi (the reconstructed variable) and two rows of
+// psi = f~+ in registers.  x-neighbours come from wave-wide DPP shifts, so no
+// LDS and no barriers are used.  Per cell and step the kernel reads the 9
+// stored values once and writes 9 values once; every face value is computed
+// once per wave (the x-face west of each lane, the y-face north of each row).
+//
+// State layout: SoA [9][ny][pitch] of the stored type S.  The stored value of
+// direction a is x_a = f~_a - w_a rho0 (rho0 = 0 gives plain f~), optionally
+// divided by w_a for 16-bit storage.  All stages are affine with coefficients
+// that sum to one, so the w_a rho0 offset cancels and every formula below runs
+// unchanged on deviations.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbfv {
+
+enum { BC_PERIODIC = 0, BC_WALL = 1, BC_INFLOW = 2, BC_OUTFLOW = 3 };
+enum { SIDE_W = 0, SIDE_E = 1, SIDE_S = 2, SIDE_N = 3 };
+enum { SCHEME_DUGKS = 0, SCHEME_BKG = 1 };
+
+// D2Q9 unit directions e_a (xi_a = c e_a, c = sqrt(3 RT)) and weights, Sec. 2.1.
+constexpr int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr int REV[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+__host__ __device__ constexpr double wgt(int a) { return a == 0 ? 4.0 / 9.0 : (a < 5 ? 1.0 / 9.0 : 1.0 / 36.0); }
+__host__ __device__ constexpr double inv_wgt(int a) { return a == 0 ? 2.25 : (a < 5 ? 9.0 : 36.0); }
+
+// Per-axis metric arrays (length 4n+2 for n cells):
+//   [0, n]        lam[f]  = (xf_f - xc_{f-1}) / (xc_f - xc_{f-1})   face f between cells f-1 and f
+//   [n+1, 2n+1]   id[f]   = 1 / (xc_f - xc_{f-1})
+//   [2n+2, 3n+1]  is[i]   = 1 / (xc_{i+1} - xc_{i-1})                central cell gradient
+//   [3n+2, 4n+1]  cd[i]   = dt c / dx_i                               flux divergence factor
+// Ghost centres: mirrored for non-periodic sides, wrapped for periodic axes.
+template <typename T>
+struct StepParams {
+    void *buf[2];           // the two state buffers; step reads buf[p], writes buf[1-p]
+    int32_t nx, ny;
+    int64_t pitch, plane;   // elements per row / per direction plane
+    const T *xm, *ym;       // metric arrays (see above)
+    int32_t bc[4];          // boundary kind per side W, E, S, N
+    T bcv[4][3];            // wall: 6 U_w / c (x, y); inflow: rho, ux / c, uy / c; outflow: order
+    T ext[4];               // linear ghost extrapolation factor per side
+    T rho0;                 // deviation reference density (0: plain storage)
+    T hc;                   // h c, h = dt / 2
+    T cb;                   // DUGKS: phi = f-bar+ = x + cb (dfeq - x)
+    T cd;                   // psi = f~+ = x + cd (dfeq - x) (also BKG's phi)
+    T m2;                   // DUGKS face back-transform f = f-bar + m2 (feq_b - f-bar)
+};
+
+// ---------------------------------------------------------------- storage
+template <typename S> struct Storage;
+// (direction indices are compile-time constants once the 9-loops are unrolled)
+template <> struct Storage<double> {
+    __device__ __forceinline__ static double load(double v, int) { return v; }
+    __device__ __forceinline__ static double store(double v, int) { return v; }
+};
+template <> struct Storage<float> {
+    __device__ __forceinline__ static float load(float v, int) { return v; }
+    __device__ __forceinline__ static float store(float v, int) { return v; }
+};
+// 16-bit storage keeps x_a / w_a (keeps FP16 values away from subnormals).
+template <> struct Storage<__bf16> {
+    __device__ __forceinline__ static float load(__bf16 v, int a) { return (float)v * (float)wgt(a); }
+    __device__ __forceinline__ static __bf16 store(float v, int a) { return (__bf16)(v * (float)inv_wgt(a)); }
+};
+template <> struct Storage<_Float16> {
+    __device__ __forceinline__ static float load(_Float16 v, int a) { return (float)v * (float)wgt(a); }
+    __device__ __forceinline__ static _Float16 store(float v, int a) { return (_Float16)(v * (float)inv_wgt(a)); }
+};
+
+// ---------------------------------------------------------------- wave shifts
+// Wave-wide DPP row moves (GFX9 wave_shr:1 / wave_shl:1).  Out-of-range lanes read 0
+// (bound_ctrl); the kernels never use those lanes' results.
+// lane i <- lane i-1
+__device__ __forceinline__ float shr1(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
+}
+// lane i <- lane i+1
+__device__ __forceinline__ float shl1(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+__device__ __forceinline__ double shr1(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x138, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x138, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double shl1(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x130, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x130, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+
+// ---------------------------------------------------------------- summation
+// Density sums: plain in FP64; in FP32 compensated (Knuth two-sum, Neumaier-style
+// running correction) so that the deviation density keeps full FP32 accuracy.
+template <typename T> struct Acc {
+    T s;
+    __device__ explicit Acc(T x) : s(x) {}
+    __device__ void add(T x) { s += x; }
+    __device__ T sum() const { return s; }
+};
+template <> struct Acc<float> {
+    float s, c;
+    __device__ explicit Acc(float x) : s(x), c(0.0f) {}
+    __device__ void add(float x) {
+        float t = s + x;
+        float z = t - s;
+        c += (s - (t - z)) + (x - z);
+        s = t;
+    }
+    __device__ float sum() const { return s + c; }
+};
+
+// ---------------------------------------------------------------- equilibrium
+// Deviation of the D2Q9 equilibrium (Sec. 2.1, Eq. equilibrium) from w_a rho0, in
+// terms of u-hat = u / c (then xi.u / RT = 3 e.u-hat, (xi.u)^2/(2 RT^2) = 4.5 (e.u-hat)^2,
+// |u|^2/(2 RT) = 1.5 |u-hat|^2):  dfeq_a = w_a (drho + rho P_a).
+template <typename T>
+__device__ __forceinline__ T usq_term(T ux, T uy) {
+    return (T)1.5 * fma(ux, ux, uy * uy);
+}
+
+// e_a . v for the unit directions (exact: additions only)
+template <typename T>
+__device__ __forceinline__ T edot(int A, T vx, T vy) {
+    const T px = EX[A] > 0 ? vx : (EX[A] < 0 ? -vx : (T)0);
+    const T py = EY[A] > 0 ? vy : (EY[A] < 0 ? -vy : (T)0);
+    return EX[A] == 0 ? py : (EY[A] == 0 ? px : px + py);
+}
+
+// The weights 1/9 and 1/36 are not binary fractions: rounded once, all of them err in
+// the same direction, which would scale the equilibrium's moments by (1 + eps) and
+// make every collision add a little momentum.  FP32 therefore multiplies by the
+// weight as a two-term (hi + lo) constant; in FP64 the bias is below the parity bar.
+template <typename T>
+__device__ __forceinline__ T wmul(int A, T q) {
+    return (T)wgt(A) * q;
+}
+template <>
+__device__ __forceinline__ float wmul<float>(int A, float q) {
+    const float hi = (float)wgt(A);
+    const float lo = (float)(wgt(A) - (double)hi);
+    return fmaf(hi, q, lo * q);
+}
+
+// The first-order term rho xi.u / RT is formed as 3 e.m from the momentum m = rho u-hat
+// itself, not as rho times (m / rho): all nine directions would otherwise share the
+// rounding of 1/rho and of rho, and the equilibrium's momentum would drift coherently
+// from step to step (measurable in FP32).
+template <typename T>
+__device__ __forceinline__ T dfeq(int A, T drho, T rho, T mx, T my, T ux, T uy, T usq15) {
+    const T eu = edot<T>(A, ux, uy);
+    const T em = edot<T>(A, mx, my);
+    const T q2 = fma((T)4.5 * eu, eu, -usq15);
+    return wmul<T>(A, fma(rho, q2, fma((T)3, em, drho)));
+}
+
+// 1 / rho.  FP64: IEEE division.  FP32: the hardware reciprocal (1 ulp); after the
+// first-order equilibrium term is formed from m directly, 1/rho only enters terms of
+// second order in u, where its last bit is far below the FP32 rounding of the state.
+template <typename T>
+__device__ __forceinline__ T recip(T r) { return (T)1 / r; }
+template <>
+__device__ __forceinline__ float recip<float>(float r) { return __builtin_amdgcn_rcpf(r); }
+
+// Moments of a 9-vector of deviations: drho = sum x, m = rho u-hat = sum e x, u-hat.
+// COMP: compensated density sum (cell moments; the face moments enter only through the
+// small back-transform weight h / (2 tau + h) and use a plain sum).
+template <typename T>
+struct Mom {
+    T drho, rho, mx, my, ux, uy, usq15;
+};
+template <typename T, bool COMP = true>
+__device__ __forceinline__ Mom<T> moments(const T (&x)[9], T rho0) {
+    Mom<T> m;
+    if (COMP) {
+        Acc<T> acc(x[0]);
+#pragma unroll
+        for (int a = 1; a < 9; ++a) acc.add(x[a]);
+        m.drho = acc.sum();
+    } else {
+        m.drho = ((x[0] + x[1]) + (x[2] + x[3])) + ((x[4] + x[5]) + (x[6] + x[7])) + x[8];
+    }
+    m.rho = rho0 + m.drho;
+    const T inv = recip(m.rho);
+    m.mx = x[1] - x[3] + x[5] - x[6] - x[7] + x[8];
+    m.my = x[2] - x[4] + x[5] + x[6] - x[7] - x[8];
+    m.ux = m.mx * inv;
+    m.uy = m.my * inv;
+    m.usq15 = usq_term(m.ux, m.uy);
+    return m;
+}
+template <typename T>
+__device__ __forceinline__ T dfeq(int A, const Mom<T> &m) {
+    return dfeq(A, m.drho, m.rho, m.mx, m.my, m.ux, m.uy, m.usq15);
+}
+
+// ---------------------------------------------------------------- the strip march
+// BND = false compiles out every ghost-cell and bounce-back path; it is used when both
+// axes are periodic (rows and columns then wrap and no wall face exists), which keeps
+// the register budget of the interior loop small.
+template <typename T, typename S, int SCHEME, bool BND>
+struct March {
+    const StepParams<T> &P;
+    const S *__restrict__ src;
+    S *__restrict__ dst;
+    int lane, col;
+    int ccol;                  // column this lane loads (wrapped / clamped)
+    bool per_x, per_y;
+    bool ghostW, ghostE;       // this wave holds the west / east ghost column
+    int laneE;                 // lane of column nx
+    // per-lane face/cell coefficients
+    T cEm, cE0, cEp, sLE;      // east face: c = lam - e_x hc id for e_x = -1, 0, +1; hc (1 - lam)
+    T cWm, cW0, cWp, sRW;      // west face: the same c; hc lam
+    T dxs;                     // hc / (xc_{i+1} - xc_{i-1})
+    T cdx;                     // dt c / dx_i
+
+    __device__ March(const StepParams<T> &p, const S *s, S *d, int x0) : P(p), src(s), dst(d) {
+        lane = threadIdx.x & 63;
+        col = x0 - 1 + lane;
+        const int nx = P.nx;
+        per_x = !BND || P.bc[SIDE_W] == BC_PERIODIC;
+        per_y = !BND || P.bc[SIDE_S] == BC_PERIODIC;
+        if (per_x) ccol = col < 0 ? col + nx : (col >= nx ? col - nx : col);
+        else ccol = col < 0 ? 0 : (col >= nx ? nx - 1 : col);
+        if (ccol >= nx) ccol = nx - 1;   // garbage lanes past a short periodic row
+        if (ccol < 0) ccol = 0;
+        ghostW = BND && !per_x && x0 == 0;
+        laneE = nx - x0 + 1;
+        ghostE = BND && !per_x && laneE <= 63;
+        const T *lam = P.xm, *id = P.xm + (nx + 1), *is = P.xm + 2 * (nx + 1), *cd = is + nx;
+        int fE = min(max(col + 1, 0), nx), fW = min(max(col, 0), nx);
+        int ci = min(max(col, 0), nx - 1);
+        const T lE = lam[fE], iE = id[fE], lW = lam[fW], iW = id[fW];
+        // face value phi_L + c (phi_R - phi_L) with c = lam - e_x h c id; both lanes that
+        // share a face compute the same c from the same metric entries
+        cE0 = lE;
+        cEp = fma(-P.hc, iE, lE);
+        cEm = fma(P.hc, iE, lE);
+        sLE = P.hc * ((T)1 - lE);
+        cW0 = lW;
+        cWp = fma(-P.hc, iW, lW);
+        cWm = fma(P.hc, iW, lW);
+        sRW = P.hc * lW;
+        dxs = P.hc * is[ci];
+        cdx = cd[ci];
+    }
+
+    __device__ __forceinline__ T cEe(int A) const { return EX[A] > 0 ? cEp : (EX[A] < 0 ? cEm : cE0); }
+    __device__ __forceinline__ T cWe(int A) const { return EX[A] > 0 ? cWp : (EX[A] < 0 ? cWm : cW0); }
+
+    // ---- row loading and the cell stage (moments, equilibrium, transforms)
+    __device__ __forceinline__ int row_index(int r) const {
+        const int ny = P.ny;
+        return r < 0 ? r + ny : (r >= ny ? r - ny : r);
+    }
+    __device__ __forceinline__ void load(int r, S (&raw)[9]) const {
+        const S *p = src + (int64_t)row_index(r) * P.pitch + ccol;
+#pragma unroll
+        for (int a = 0; a < 9; ++a) raw[a] = p[a * P.plane];
+    }
+    // phi (and psi for DUGKS) of one row from its stored values.  Sec. 2.2: psi =
+    // f~+ = x + cd (dfeq - x); f-bar+ = x + cb (dfeq - x) (closed forms after eliminating
+    // f = (2 tau f~ + dt feq)/(2 tau + dt)); BKG uses phi = f~+ (Sec. 2.3, 2.5).  The
+    // relaxation form keeps an equilibrium exactly fixed in any precision.
+    __device__ __forceinline__ void cell(const S (&raw)[9], T (&phi)[9], T (&psi)[9]) const {
+        T x[9];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            x[a] = Storage<S>::load(raw[a], a);
+        }
+        const Mom<T> m = moments(x, P.rho0);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            const T d = dfeq(a, m) - x[a];
+            if (SCHEME == SCHEME_DUGKS) {
+                phi[a] = fma(P.cb, d, x[a]);
+                psi[a] = fma(P.cd, d, x[a]);
+            } else {
+                phi[a] = fma(P.cd, d, x[a]);
+            }
+        }
+    }
+
+    // ---- ghost cells (Sec. 2.5, readings R5 / R6): one ghost value per direction from
+    // the two nearest interior values g1 (adjacent) and g2 (next).
+    __device__ __forceinline__ T ghost_rule(int A, int side, T g1, T g2) const {
+        const int k = P.bc[side];
+        if (k == BC_INFLOW) {
+            const T rho = P.bcv[side][0], ux = P.bcv[side][1], uy = P.bcv[side][2];
+            return dfeq(A, rho - P.rho0, rho, rho * ux, rho * uy, ux, uy, usq_term(ux, uy));
+        }
+        if (k == BC_OUTFLOW && P.bcv[side][0] < (T)0.5) return g1;
+        return fma(g1 - g2, P.ext[side], g1);   // wall and first-order outflow
+    }
+    // x-side ghost lanes of one row (x-sides first, as in Sec. 2.5 reading R5)
+    __device__ __forceinline__ void ghost_x(T (&phi)[9]) const {
+        if (ghostW) {
+#pragma unroll
+            for (int a = 0; a < 9; ++a) {
+                T g1 = shl1(phi[a]), g2 = shl1(g1);
+                T g = ghost_rule(a, SIDE_W, g1, g2);
+                phi[a] = lane == 0 ? g : phi[a];
+            }
+        }
+        if (ghostE) {
+#pragma unroll
+            for (int a = 0; a < 9; ++a) {
+                T g1 = shr1(phi[a]), g2 = shr1(g1);
+                T g = ghost_rule(a, SIDE_E, g1, g2);
+                phi[a] = lane == laneE ? g : phi[a];
+            }
+        }
+    }
+    // y-side ghost row from rows r1 (adjacent) and r2 (next); ghost lanes included (corners)
+    __device__ __forceinline__ void ghost_y(int side, const T (&r1)[9], const T (&r2)[9], T (&out)[9]) const {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            out[a] = ghost_rule(a, side, r1[a], r2[a]);
+        }
+    }
+
+    // ---- half-way bounce-back (Sec. 2.5): for each direction leaving the fluid through
+    // the face (e.n_out > 0) the reverse value is phi_a - 2 w_a xi_a.U_w / c_s^2,
+    // with rho_w = 1 (reading R4); bx, by hold 6 U_w / c.
+    template <int NX, int NY>
+    __device__ __forceinline__ void bounce(T (&fb)[9], T bx, T by, bool on) const {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            if (EX[a] * NX + EY[a] * NY > 0) {
+                const T v = fma(-(T)wgt(a), edot<T>(a, bx, by), fb[a]);
+                fb[REV[a]] = on ? v : fb[REV[a]];
+            }
+        }
+    }
+
+    // ---- DUGKS interface distribution (Sec. 2.2): face moments of f-bar, feq_b, then
+    // f = (2 tau f-bar + h feq_b)/(2 tau + h) for the directions with flux through the face.
+    template <int AX>
+    __device__ __forceinline__ void face_mix(T (&fb)[9]) const {
+        if (SCHEME == SCHEME_DUGKS) {
+            const Mom<T> m = moments<T, false>(fb, P.rho0);
+#pragma unroll
+            for (int a = 0; a < 9; ++a) {
+                if ((AX == 0 ? EX[a] : EY[a]) != 0) {
+                    const T fe = dfeq(a, m);
+                    fb[a] = fma(P.m2, fe - fb[a], fb[a]);
+                }
+            }
+        }
+    }
+
+    // ---- y-face between rows (S = lo, N = hi): face index g; half-step trace of Eq. f_left
+    // with tangential gradient from neighbouring lanes, Sec. 2.2 / 2.3 (readings R2 / R3).
+    __device__ __forceinline__ void yface(int g, const T (&lo)[9], const T (&hi)[9], T (&fb)[9]) const {
+        const int ny = P.ny;
+        const T lam = P.ym[g];
+        const T bn = P.hc * P.ym[ny + 1 + g];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            const T dn = hi[a] - lo[a];
+            const T q = fma(lam, dn, lo[a]);
+            T v = q;
+            if (EY[a] != 0) v = fma(EY[a] > 0 ? -bn : bn, dn, v);
+            if (EX[a] != 0) v = fma(EX[a] > 0 ? -dxs : dxs, shl1(q) - shr1(q), v);
+            fb[a] = v;
+        }
+    }
+
+    // ---- x-face west of each lane at the current row; sy = cell d/dy of phi
+    __device__ __forceinline__ void xface(const T (&phi)[9], const T (&sy)[9], T (&fb)[9]) const {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            // left cell's share (1 - c) phi_L - e_y hc (1 - lam) sigma_L, formed in the
+            // left lane and shifted right
+            T part = fma(-cEe(a), phi[a], phi[a]);
+            if (EY[a] != 0) part = fma(EY[a] > 0 ? -sLE : sLE, sy[a], part);
+            T v = fma(cWe(a), phi[a], shr1(part));
+            if (EY[a] != 0) v = fma(EY[a] > 0 ? -sRW : sRW, sy[a], v);
+            fb[a] = v;
+        }
+    }
+
+    // ---- one output row k.  Pm, P0, Pp = phi rows k-1, k, k+1; S0 = psi row k;
+    // fS = y-face values south of row k.  Produces the row-k update and the
+    // y-face values north of row k (left in fS).  If a next row is needed its
+    // phi / psi go to Pm / Sm.
+    __device__ __forceinline__ void body(int k, int j1, T (&Pm)[9], T (&P0)[9], T (&Pp)[9], T (&Sm)[9],
+                                         T (&S0)[9], T (&fS)[9]) {
+        const int ny = P.ny;
+        const bool need_next = k + 1 < j1;
+        const bool next_real = !BND || (k + 2 < ny) || per_y;
+        S raw[9];
+        if (need_next && next_real) load(k + 2, raw);
+
+        // x-faces at row k
+        T sy[9];
+        const T isy = P.ym[2 * (ny + 1) + k];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            if (EY[a] != 0) sy[a] = (Pp[a] - Pm[a]) * isy;
+            else sy[a] = (T)0;
+        }
+        T fW[9];
+        xface(P0, sy, fW);
+        if (ghostW && P.bc[SIDE_W] == BC_WALL)
+            bounce<-1, 0>(fW, P.bcv[SIDE_W][0], P.bcv[SIDE_W][1], lane == 1);
+        if (ghostE && P.bc[SIDE_E] == BC_WALL)
+            bounce<1, 0>(fW, P.bcv[SIDE_E][0], P.bcv[SIDE_E][1], lane == laneE);
+        face_mix<0>(fW);
+
+        // y-face north of row k
+        T fN[9];
+        yface(k + 1, P0, Pp, fN);
+        if (BND && k + 1 == ny && P.bc[SIDE_N] == BC_WALL) bounce<0, 1>(fN, P.bcv[SIDE_N][0], P.bcv[SIDE_N][1], true);
+        face_mix<1>(fN);
+
+        // flux divergence and update, Eq. eq_update with the sign of Eq. bkg_fv (reading R1)
+        const T cdy = P.ym[3 * ny + 2 + k];
+        const bool st = lane >= 1 && lane <= 62 && col < P.nx;
+        S *out = dst + (int64_t)k * P.pitch + col;
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            T v = (SCHEME == SCHEME_DUGKS) ? S0[a] : P0[a];
+            if (EX[a] != 0) {
+                const T fE = shl1(fW[a]);
+                v = fma(EX[a] > 0 ? -cdx : cdx, fE - fW[a], v);
+            }
+            if (EY[a] != 0) v = fma(EY[a] > 0 ? -cdy : cdy, fN[a] - fS[a], v);
+            if (st) out[a * P.plane] = Storage<S>::store(v, a);
+        }
+#pragma unroll
+        for (int a = 0; a < 9; ++a) fS[a] = fN[a];
+
+        // next row (k + 2) into the free slot
+        if (need_next) {
+            if (next_real) {
+                cell(raw, Pm, Sm);
+                ghost_x(Pm);
+            } else {
+                ghost_y(SIDE_N, Pp, P0, Pm);
+            }
+        }
+    }
+
+    __device__ __forceinline__ void run(int j0, int j1) {
+        const int ny = P.ny;
+        T PA[9], PB[9], PC[9], SA[9], SB[9], SC[9], fS[9];
+        S raw[9];
+        // prologue: PA = phi[j0-1], PB = phi[j0], PC = phi[j0+1], SB / SC = psi
+        if (BND && j0 == 0 && !per_y) {
+            load(0, raw);
+            cell(raw, PB, SB);
+            ghost_x(PB);
+            load(1, raw);
+            cell(raw, PC, SC);
+            ghost_x(PC);
+            ghost_y(SIDE_S, PB, PC, PA);
+        } else {
+            load(j0 - 1, raw);
+            cell(raw, PA, SA);
+            ghost_x(PA);
+            load(j0, raw);
+            cell(raw, PB, SB);
+            ghost_x(PB);
+            if (!BND || j0 + 1 < ny || per_y) {
+                load(j0 + 1, raw);
+                cell(raw, PC, SC);
+                ghost_x(PC);
+            } else {
+                ghost_y(SIDE_N, PB, PA, PC);
+            }
+        }
+        yface(j0, PA, PB, fS);
+        if (BND && j0 == 0 && P.bc[SIDE_S] == BC_WALL) bounce<0, -1>(fS, P.bcv[SIDE_S][0], P.bcv[SIDE_S][1], true);
+        face_mix<1>(fS);
+
+        for (int k = j0; k < j1; k += 3) {
+            body(k, j1, PA, PB, PC, SA, SB, fS);
+            if (k + 1 >= j1) break;
+            body(k + 1, j1, PB, PC, PA, SB, SC, fS);
+            if (k + 2 >= j1) break;
+            body(k + 2, j1, PC, PA, PB, SC, SA, fS);
+        }
+    }
+};
+
+// One launch = one time step of one case.  Work item w -> (strip, row block); each wave
+// takes one item.  Blocks are renumbered so that consecutive work lands on the same XCD
+// (the hardware deals blocks to the 8 XCDs round-robin).
+template <typename T, typename S, int SCHEME, bool BND>
+__global__ __launch_bounds__(256) void step_kernel(StepParams<T> P, int parity, int rows, int nstrips,
+                                                   int nwork) {
+    const int nb = gridDim.x;
+    int b = blockIdx.x;
+    const int per = (nb + 7) / 8;
+    const int xcd = b % 8, slot = b / 8;
+    const int full = nb % 8 == 0 ? 8 : nb % 8;   // XCDs that receive `per` blocks
+    int rb = xcd < full ? xcd * per + slot : full * per + (xcd - full) * (per - 1) + slot;
+    if (nb < 16) rb = b;
+    const int wpb = blockDim.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(rb * wpb + (int)(threadIdx.x >> 6));
+    if (w >= nwork) return;
+    const int sx = w % nstrips, sy = w / nstrips;
+    const int j0 = sy * rows, j1 = min(P.ny, j0 + rows);
+    const S *src = (const S *)P.buf[parity];
+    S *dst = (S *)P.buf[parity ^ 1];
+    March<T, S, SCHEME, BND> m(P, src, dst, 62 * sx);
+    m.run(j0, j1);
+}
+
+// Work item of the batched form: case id, strip x0, rows [j0, j1).
+struct BatchItem {
+    int32_t c, x0, j0, j1;
+};
+
+// Batched persistent form: every wave walks the flat work list over all cases with a
+// grid stride; each case carries its own mesh, tau, dt, boundaries and buffers.
+template <typename T, typename S, int SCHEME, bool BND>
+__global__ __launch_bounds__(256) void batch_kernel(const StepParams<T> *__restrict__ cases,
+                                                    const BatchItem *__restrict__ items, int nitems,
+                                                    int parity) {
+    const int wpb = blockDim.x >> 6;
+    const int nw = gridDim.x * wpb;
+    int w = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (int)(threadIdx.x >> 6));
+    for (; w < nitems; w += nw) {
+        const BatchItem it = items[w];
+        const StepParams<T> P = cases[it.c];
+        const S *src = (const S *)P.buf[parity];
+        S *dst = (S *)P.buf[parity ^ 1];
+        March<T, S, SCHEME, BND> m(P, src, dst, it.x0);
+        m.run(it.j0, it.j1);
+    }
+}
+
+}  // namespace lbfv

@@ -1,0 +1,1419 @@
+// lbfv.hip -- host side of liblbfv: contexts, mesh metrics, boundary descriptors,
+// launch shapes, HIP graphs, checks, observables, the autotuner and the batched form.
+// The public ABI is include/lbfv.h.
+#include "lbfv.h"
+#include "aux_kernels.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+using namespace lbfv;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+enum Variant { V_F64 = 0, V_F32 = 1, V_BF16 = 2, V_F16 = 3 };
+
+struct HostCase {
+    int nx = 0, ny = 0;
+    std::vector<double> xf, yf;
+    double rt = 1.0 / 3.0, c = 1.0, tau = 1.0, dt = 1.0;
+    int bc[4] = {-1, -1, -1, -1};
+    double bcval[4][3] = {};
+    int variant = V_F64;
+    double rho0 = 0.0;        // 0 for native storage
+    int64_t pitch = 0, plane = 0;
+    size_t esize = 8;
+    void *buf[2] = {nullptr, nullptr};
+    bool own = true;
+    int cur = 0;              // buffer holding the current state
+    void *d_xm = nullptr, *d_ym = nullptr;   // metrics in the compute type
+    double *d_dx = nullptr, *d_dy = nullptr; // cell sizes (FP64) for volumes
+    bool metrics_dirty = true;
+
+    size_t buffer_bytes() const { return (size_t)plane * 9 * esize; }
+    bool sides_set() const { return bc[0] >= 0 && bc[1] >= 0 && bc[2] >= 0 && bc[3] >= 0; }
+    bool periodic_x() const { return bc[SIDE_W] == BC_PERIODIC; }
+    bool periodic_y() const { return bc[SIDE_S] == BC_PERIODIC; }
+};
+
+#define HIPCHK(expr)                                                                            \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess) {                                                                 \
+            return c->fail(LBFV_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));       \
+        }                                                                                       \
+    } while (0)
+
+}  // namespace
+
+struct lbfv_ctx {
+    HostCase hc;
+    int check_every = 1000;
+    hipStream_t stream = nullptr;
+    bool has_state = false;
+    bool unstable = false;
+    int64_t steps = 0, steps_at_check = 0;
+    int rows = 0, wpb = 4;
+    // graphs of `gsteps` launches, per scheme and starting buffer
+    int gsteps = 32;
+    hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    // reductions
+    double *d_partial = nullptr, *d_out = nullptr, *h_out = nullptr, *d_uprev = nullptr;
+    int red_blocks = 0;
+    bool check_pending = false;
+    hipEvent_t check_event = nullptr;
+    bool uprev_valid = false;
+    std::string last_error;
+
+    int fail(int status, const std::string &msg) {
+        last_error = msg;
+        g_last_error = msg;
+        return status;
+    }
+};
+
+struct lbfv_batch {
+    std::vector<HostCase> cases;
+    int variant = V_F32;
+    double rho0 = 1.0;
+    hipStream_t stream = nullptr;
+    void *d_params = nullptr;        // StepParams<T>[n]
+    BatchItem *d_items = nullptr;
+    int nitems = 0, rows = 16, gsteps = 100;
+    int parity = 0;                  // all cases share the step parity
+    bool bnd = false;                // some case has a non-periodic side
+    hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    bool has_state = false;
+    std::string last_error;
+    int fail(int status, const std::string &msg) {
+        last_error = msg;
+        g_last_error = msg;
+        return status;
+    }
+};
+
+namespace {
+
+// ------------------------------------------------------------------ metrics
+// Cell centres with one ghost on each side: mirrored for walls / inflow / outflow,
+// wrapped for a periodic axis (the ghost takes the size of the wrapped cell).
+void axis_metrics(const std::vector<double> &f, bool periodic, double dt, double c, std::vector<double> &m,
+                  double &ext_lo, double &ext_hi, std::vector<double> &sizes) {
+    const int n = (int)f.size() - 1;
+    std::vector<double> xc(n + 2);   // xc[i + 1], i = -1..n
+    sizes.resize(n);
+    for (int i = 0; i < n; ++i) {
+        sizes[i] = f[i + 1] - f[i];
+        xc[i + 1] = 0.5 * (f[i] + f[i + 1]);
+    }
+    if (periodic) {
+        xc[0] = f[0] - 0.5 * sizes[n - 1];
+        xc[n + 1] = f[n] + 0.5 * sizes[0];
+    } else {
+        xc[0] = f[0] - 0.5 * sizes[0];
+        xc[n + 1] = f[n] + 0.5 * sizes[n - 1];
+    }
+    auto X = [&](int i) { return xc[i + 1]; };
+    m.assign(4 * n + 2, 0.0);
+    for (int g = 0; g <= n; ++g) {
+        const double d = X(g) - X(g - 1);
+        m[g] = (f[g] - X(g - 1)) / d;
+        m[n + 1 + g] = 1.0 / d;
+    }
+    for (int i = 0; i < n; ++i) {
+        m[2 * n + 2 + i] = 1.0 / (X(i + 1) - X(i - 1));
+        m[3 * n + 2 + i] = dt * c / sizes[i];
+    }
+    ext_lo = (X(0) - X(-1)) / (X(1) - X(0));
+    ext_hi = (X(n) - X(n - 1)) / (X(n - 1) - X(n - 2));
+}
+
+template <typename T>
+void copy_as(const std::vector<double> &in, std::vector<T> &out) {
+    out.resize(in.size());
+    for (size_t i = 0; i < in.size(); ++i) out[i] = (T)in[i];
+}
+
+template <typename T>
+StepParams<T> make_params(const HostCase &h, double ext[4]) {
+    StepParams<T> P;
+    memset(&P, 0, sizeof(P));
+    P.buf[0] = h.buf[0];
+    P.buf[1] = h.buf[1];
+    P.nx = h.nx;
+    P.ny = h.ny;
+    P.pitch = h.pitch;
+    P.plane = h.plane;
+    P.xm = (const T *)h.d_xm;
+    P.ym = (const T *)h.d_ym;
+    for (int s = 0; s < 4; ++s) {
+        P.bc[s] = h.bc[s];
+        P.ext[s] = (T)ext[s];
+        if (h.bc[s] == BC_WALL) {
+            P.bcv[s][0] = (T)(6.0 * h.bcval[s][0] / h.c);
+            P.bcv[s][1] = (T)(6.0 * h.bcval[s][1] / h.c);
+        } else if (h.bc[s] == BC_INFLOW) {
+            P.bcv[s][0] = (T)h.bcval[s][0];
+            P.bcv[s][1] = (T)(h.bcval[s][1] / h.c);
+            P.bcv[s][2] = (T)(h.bcval[s][2] / h.c);
+        } else if (h.bc[s] == BC_OUTFLOW) {
+            P.bcv[s][0] = (T)h.bcval[s][0];
+        }
+    }
+    const double tau = h.tau, dt = h.dt, hh = 0.5 * dt;
+    P.rho0 = (T)h.rho0;
+    P.hc = (T)(hh * h.c);
+    P.cb = (T)(3.0 * hh / (2.0 * tau + dt));
+    P.cd = (T)(2.0 * dt / (2.0 * tau + dt));
+    P.m2 = (T)(hh / (2.0 * tau + hh));
+    return P;
+}
+
+bool is_f64(int v) { return v == V_F64; }
+
+// (Re)build and upload the per-axis metric arrays of a case.  Returns a HIP error.
+hipError_t upload_metrics(HostCase &h, double ext[4], hipStream_t s) {
+    std::vector<double> mx, my, sx, sy;
+    axis_metrics(h.xf, h.periodic_x(), h.dt, h.c, mx, ext[SIDE_W], ext[SIDE_E], sx);
+    axis_metrics(h.yf, h.periodic_y(), h.dt, h.c, my, ext[SIDE_S], ext[SIDE_N], sy);
+    const size_t tsz = is_f64(h.variant) ? 8 : 4;
+    hipError_t e;
+    if (!h.d_xm) {
+        if ((e = hipMalloc(&h.d_xm, mx.size() * tsz)) != hipSuccess) return e;
+        if ((e = hipMalloc(&h.d_ym, my.size() * tsz)) != hipSuccess) return e;
+        if ((e = hipMalloc((void **)&h.d_dx, sx.size() * 8)) != hipSuccess) return e;
+        if ((e = hipMalloc((void **)&h.d_dy, sy.size() * 8)) != hipSuccess) return e;
+    }
+    if (tsz == 8) {
+        if ((e = hipMemcpyAsync(h.d_xm, mx.data(), mx.size() * 8, hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(h.d_ym, my.data(), my.size() * 8, hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+    } else {
+        std::vector<float> fx, fy;
+        copy_as(mx, fx);
+        copy_as(my, fy);
+        if ((e = hipMemcpyAsync(h.d_xm, fx.data(), fx.size() * 4, hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(h.d_ym, fy.data(), fy.size() * 4, hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+    }
+    if ((e = hipMemcpyAsync(h.d_dx, sx.data(), sx.size() * 8, hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(h.d_dy, sy.data(), sy.size() * 8, hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+    // the host vectors die here: wait for the copies
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    h.metrics_dirty = false;
+    return hipSuccess;
+}
+
+void free_case(HostCase &h) {
+    if (h.own) {
+        if (h.buf[0]) (void)hipFree(h.buf[0]);
+        if (h.buf[1]) (void)hipFree(h.buf[1]);
+    }
+    h.buf[0] = h.buf[1] = nullptr;
+    if (h.d_xm) (void)hipFree(h.d_xm);
+    if (h.d_ym) (void)hipFree(h.d_ym);
+    if (h.d_dx) (void)hipFree(h.d_dx);
+    if (h.d_dy) (void)hipFree(h.d_dy);
+    h.d_xm = h.d_ym = nullptr;
+    h.d_dx = h.d_dy = nullptr;
+}
+
+// ------------------------------------------------------------------ kernel dispatch
+struct StepShape {
+    int rows, wpb, nstrips, nwork, nblocks;
+};
+StepShape step_shape(const HostCase &h, int rows, int wpb) {
+    StepShape s;
+    s.rows = rows;
+    s.wpb = wpb;
+    s.nstrips = (h.nx + 61) / 62;
+    s.nwork = s.nstrips * ((h.ny + rows - 1) / rows);
+    s.nblocks = (s.nwork + wpb - 1) / wpb;
+    return s;
+}
+
+template <typename T, typename S, bool BND>
+void *step_fn_b(int scheme) {
+    return scheme == SCHEME_DUGKS ? (void *)step_kernel<T, S, SCHEME_DUGKS, BND>
+                                  : (void *)step_kernel<T, S, SCHEME_BKG, BND>;
+}
+template <typename T, typename S>
+void *step_fn(int scheme, bool bnd) {
+    return bnd ? step_fn_b<T, S, true>(scheme) : step_fn_b<T, S, false>(scheme);
+}
+// bnd: some side is not periodic (ghost cells / walls present)
+void *step_fn_variant(int variant, int scheme, bool bnd) {
+    switch (variant) {
+    case V_F64: return step_fn<double, double>(scheme, bnd);
+    case V_F32: return step_fn<float, float>(scheme, bnd);
+    case V_BF16: return step_fn<float, __bf16>(scheme, bnd);
+    default: return step_fn<float, _Float16>(scheme, bnd);
+    }
+}
+template <typename T, typename S, bool BND>
+void *batch_fn_b(int scheme) {
+    return scheme == SCHEME_DUGKS ? (void *)batch_kernel<T, S, SCHEME_DUGKS, BND>
+                                  : (void *)batch_kernel<T, S, SCHEME_BKG, BND>;
+}
+template <typename T, typename S>
+void *batch_fn(int scheme, bool bnd) {
+    return bnd ? batch_fn_b<T, S, true>(scheme) : batch_fn_b<T, S, false>(scheme);
+}
+void *batch_fn_variant(int variant, int scheme, bool bnd) {
+    switch (variant) {
+    case V_F64: return batch_fn<double, double>(scheme, bnd);
+    case V_F32: return batch_fn<float, float>(scheme, bnd);
+    case V_BF16: return batch_fn<float, __bf16>(scheme, bnd);
+    default: return batch_fn<float, _Float16>(scheme, bnd);
+    }
+}
+
+bool has_boundary(const HostCase &h) { return !(h.periodic_x() && h.periodic_y()); }
+
+// Kernel arguments of one step launch, in a form usable by hipLaunchKernel and by
+// graph kernel nodes.
+struct StepArgs {
+    StepParams<double> pd;
+    StepParams<float> pf;
+    int parity, rows, nstrips, nwork;
+    void *args[5];
+    void bind(bool f64) {
+        args[0] = f64 ? (void *)&pd : (void *)&pf;
+        args[1] = &parity;
+        args[2] = &rows;
+        args[3] = &nstrips;
+        args[4] = &nwork;
+    }
+};
+
+void fill_args(const HostCase &h, const double ext[4], const StepShape &sh, int parity, StepArgs &a) {
+    double e[4] = {ext[0], ext[1], ext[2], ext[3]};
+    if (is_f64(h.variant)) a.pd = make_params<double>(h, e);
+    else a.pf = make_params<float>(h, e);
+    a.parity = parity;
+    a.rows = sh.rows;
+    a.nstrips = sh.nstrips;
+    a.nwork = sh.nwork;
+    a.bind(is_f64(h.variant));
+}
+
+// Wave slots the step kernel can keep resident on the whole device (CUs x waves per CU).
+int resident_waves(void *fn, int wpb) {
+    int dev = 0, blocks = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, (const void *)fn, 64 * wpb, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return blocks * wpb * p.multiProcessorCount;
+}
+
+// Row-block heights whose wave count fills the resident slots in k whole rounds:
+// few prologue rows re-read and no partial last round.
+std::vector<int> balanced_rows(const HostCase &h, int slots) {
+    std::vector<int> out;
+    if (slots <= 0) return out;
+    const int nstrips = (h.nx + 61) / 62;
+    for (int k = 1; k <= 4; ++k) {
+        const int blocks = (k * slots) / nstrips;   // row blocks per strip
+        if (blocks < 1) continue;
+        const int r = (h.ny + blocks - 1) / blocks;
+        if (r >= 4 && r <= h.ny) out.push_back(r);
+    }
+    return out;
+}
+
+int default_rows(const HostCase &h, int scheme, int wpb) {
+    const int64_t cells = (int64_t)h.nx * h.ny;
+    if (cells >= (1 << 22)) {
+        // large meshes: one round of resident waves
+        const bool bnd = !(h.periodic_x() && h.periodic_y());
+        auto r = balanced_rows(h, resident_waves(step_fn_variant(h.variant, scheme, bnd), wpb));
+        if (!r.empty()) return r[0];
+        return std::min(64, h.ny);
+    }
+    return std::min(cells >= (1 << 18) ? 16 : 8, h.ny);
+}
+
+}  // namespace
+
+// ====================================================================== context
+extern "C" {
+
+const char *lbfv_strerror(int status) {
+    switch (status) {
+    case LBFV_OK: return "ok";
+    case LBFV_EINVAL: return "invalid argument";
+    case LBFV_ESTATE: return "invalid state for this call";
+    case LBFV_ENOMEM: return "out of memory";
+    case LBFV_EHIP: return "HIP runtime error";
+    case LBFV_EUNSTABLE: return "non-finite value found (unstable run)";
+    case LBFV_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+const char *lbfv_last_error(const lbfv_ctx *ctx) {
+    return ctx ? ctx->last_error.c_str() : g_last_error.c_str();
+}
+
+int lbfv_dt_from_cfl(const lbfv_mesh *mesh, double rt, double cfl, double *dt) {
+    if (!mesh || !dt || !mesh->xf || !mesh->yf || mesh->nx < 1 || mesh->ny < 1 || !(rt > 0) || !(cfl > 0)) {
+        g_last_error = "lbfv_dt_from_cfl: bad argument";
+        return LBFV_EINVAL;
+    }
+    double dmin = INFINITY;
+    for (int i = 0; i < mesh->nx; ++i) dmin = std::min(dmin, mesh->xf[i + 1] - mesh->xf[i]);
+    for (int j = 0; j < mesh->ny; ++j) dmin = std::min(dmin, mesh->yf[j + 1] - mesh->yf[j]);
+    if (!(dmin > 0)) {
+        g_last_error = "lbfv_dt_from_cfl: faces not strictly increasing";
+        return LBFV_EINVAL;
+    }
+    *dt = cfl * dmin / std::sqrt(6.0 * rt);
+    return LBFV_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+int validate_case(const lbfv_mesh *mesh, const lbfv_velset *vel, double tau, double dt, int compute, int storage,
+                  std::string &msg) {
+    if (!mesh || !vel) { msg = "NULL mesh or velocity set"; return LBFV_EINVAL; }
+    if (mesh->nx < 2 || mesh->ny < 2) { msg = "nx and ny must be >= 2"; return LBFV_EINVAL; }
+    if (!mesh->xf || !mesh->yf) { msg = "NULL face coordinates"; return LBFV_EINVAL; }
+    for (int i = 0; i < mesh->nx; ++i)
+        if (!(mesh->xf[i + 1] > mesh->xf[i])) { msg = "x faces not strictly increasing"; return LBFV_EINVAL; }
+    for (int j = 0; j < mesh->ny; ++j)
+        if (!(mesh->yf[j + 1] > mesh->yf[j])) { msg = "y faces not strictly increasing"; return LBFV_EINVAL; }
+    if (vel->q != 9) { msg = "only D2Q9 (q = 9) is provided"; return LBFV_EINVAL; }
+    if (!(vel->rt > 0) || !std::isfinite(vel->rt)) { msg = "rt must be > 0"; return LBFV_EINVAL; }
+    if (!(tau > 0) || !(dt > 0) || !std::isfinite(dt)) { msg = "tau and dt must be > 0"; return LBFV_EINVAL; }
+    if (compute != LBFV_FP64 && compute != LBFV_FP32) { msg = "compute must be LBFV_FP64 or LBFV_FP32"; return LBFV_EINVAL; }
+    if (storage < LBFV_STORE_NATIVE || storage > LBFV_STORE_DEV_FP16) { msg = "unknown storage"; return LBFV_EINVAL; }
+    if (compute == LBFV_FP64 && storage != LBFV_STORE_NATIVE) {
+        msg = "deviation / 16-bit storage needs FP32 compute";
+        return LBFV_EINVAL;
+    }
+    return LBFV_OK;
+}
+
+void init_host_case(HostCase &h, const lbfv_mesh *mesh, const lbfv_velset *vel, double tau, double dt, int compute,
+                    int storage, double rho0) {
+    h.nx = mesh->nx;
+    h.ny = mesh->ny;
+    h.xf.assign(mesh->xf, mesh->xf + mesh->nx + 1);
+    h.yf.assign(mesh->yf, mesh->yf + mesh->ny + 1);
+    h.rt = vel->rt;
+    h.c = std::sqrt(3.0 * vel->rt);
+    h.tau = tau;
+    h.dt = dt;
+    if (compute == LBFV_FP64) h.variant = V_F64;
+    else if (storage == LBFV_STORE_DEV_BF16) h.variant = V_BF16;
+    else if (storage == LBFV_STORE_DEV_FP16) h.variant = V_F16;
+    else h.variant = V_F32;
+    h.rho0 = storage == LBFV_STORE_NATIVE ? 0.0 : rho0;
+    h.esize = h.variant == V_F64 ? 8 : (h.variant == V_F32 ? 4 : 2);
+    h.pitch = ((int64_t)h.nx + 63) / 64 * 64;
+    h.plane = h.pitch * h.ny;
+}
+
+int set_side(HostCase &h, int side, int kind, double a, double b, double c) {
+    if (side < 0 || side > 3) return LBFV_EINVAL;
+    // a periodic axis is set as a whole: replacing one side of it clears the other
+    const int other = side ^ 1;
+    if (h.bc[side] == BC_PERIODIC && kind != BC_PERIODIC && h.bc[other] == BC_PERIODIC) h.bc[other] = -1;
+    h.bc[side] = kind;
+    h.bcval[side][0] = a;
+    h.bcval[side][1] = b;
+    h.bcval[side][2] = c;
+    h.metrics_dirty = true;
+    return LBFV_OK;
+}
+
+}  // namespace
+
+// internal helpers operating on a context
+namespace {
+
+void drop_graphs(lbfv_ctx *c) {
+    for (auto &row : c->gexec)
+        for (auto &g : row)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+}
+
+int ensure_buffers(lbfv_ctx *c) {
+    HostCase &h = c->hc;
+    if (h.buf[0]) return LBFV_OK;
+    const size_t bytes = h.buffer_bytes();
+    if (hipMalloc(&h.buf[0], bytes) != hipSuccess || hipMalloc(&h.buf[1], bytes) != hipSuccess) {
+        if (h.buf[0]) (void)hipFree(h.buf[0]);
+        h.buf[0] = h.buf[1] = nullptr;
+        (void)hipGetLastError();
+        return c->fail(LBFV_ENOMEM, "cannot allocate the two state buffers");
+    }
+    h.own = true;
+    // padding columns are never read by the step, but keep them defined
+    HIPCHK(hipMemsetAsync(h.buf[0], 0, bytes, c->stream));
+    HIPCHK(hipMemsetAsync(h.buf[1], 0, bytes, c->stream));
+    drop_graphs(c);
+    return LBFV_OK;
+}
+
+int ensure_metrics(lbfv_ctx *c, double ext[4]) {
+    HostCase &h = c->hc;
+    if (h.metrics_dirty) {
+        if (!h.sides_set()) return c->fail(LBFV_ESTATE, "all four sides must be set");
+        HIPCHK(upload_metrics(h, ext, c->stream));
+        drop_graphs(c);
+    }
+    return LBFV_OK;
+}
+
+// current extrapolation factors (recomputed on the host; cheap)
+void current_ext(const HostCase &h, double ext[4]) {
+    std::vector<double> m, s;
+    axis_metrics(h.xf, h.periodic_x(), h.dt, h.c, m, ext[SIDE_W], ext[SIDE_E], s);
+    axis_metrics(h.yf, h.periodic_y(), h.dt, h.c, m, ext[SIDE_S], ext[SIDE_N], s);
+}
+
+int launch_one(lbfv_ctx *c, int scheme, int parity, const double ext[4]) {
+    HostCase &h = c->hc;
+    StepShape sh = step_shape(h, c->rows, c->wpb);
+    StepArgs a;
+    fill_args(h, ext, sh, parity, a);
+    HIPCHK(hipLaunchKernel(step_fn_variant(h.variant, scheme, has_boundary(h)), dim3(sh.nblocks), dim3(64 * sh.wpb), a.args, 0,
+                           c->stream));
+    return LBFV_OK;
+}
+
+int build_graph(lbfv_ctx *c, int scheme, int parity0, const double ext[4]) {
+    HostCase &h = c->hc;
+    StepShape sh = step_shape(h, c->rows, c->wpb);
+    hipGraph_t g;
+    HIPCHK(hipGraphCreate(&g, 0));
+    hipGraphNode_t prev = nullptr;
+    for (int s = 0; s < c->gsteps; ++s) {
+        StepArgs a;
+        fill_args(h, ext, sh, (parity0 + s) & 1, a);
+        hipKernelNodeParams kp;
+        memset(&kp, 0, sizeof(kp));
+        kp.func = step_fn_variant(h.variant, scheme, has_boundary(h));
+        kp.gridDim = dim3(sh.nblocks);
+        kp.blockDim = dim3(64 * sh.wpb);
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = a.args;
+        kp.extra = nullptr;
+        hipGraphNode_t node;
+        hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return c->fail(LBFV_EHIP, std::string("hipGraphAddKernelNode: ") + hipGetErrorString(e));
+        }
+        prev = node;
+    }
+    hipError_t e = hipGraphInstantiate(&c->gexec[scheme][parity0], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return c->fail(LBFV_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    return LBFV_OK;
+}
+
+int ensure_reduction(lbfv_ctx *c) {
+    if (c->d_partial) return LBFV_OK;
+    c->red_blocks = 1024;
+    HIPCHK(hipMalloc((void **)&c->d_partial, sizeof(double) * RED_N * c->red_blocks));
+    HIPCHK(hipMalloc((void **)&c->d_out, sizeof(double) * RED_N));
+    HIPCHK(hipHostMalloc((void **)&c->h_out, sizeof(double) * RED_N, hipHostMallocDefault));
+    HIPCHK(hipEventCreateWithFlags(&c->check_event, hipEventDisableTiming));
+    return LBFV_OK;
+}
+
+template <typename T, typename S>
+void launch_reduce_t(lbfv_ctx *c, const double ext[4], int mode) {
+    HostCase &h = c->hc;
+    double e[4] = {ext[0], ext[1], ext[2], ext[3]};
+    StepParams<T> P = make_params<T>(h, e);
+    hipLaunchKernelGGL((reduce_kernel<T, S>), dim3(c->red_blocks), dim3(RED_BLOCK), 0, c->stream, P, h.cur, h.d_dx,
+                       h.d_dy, c->d_uprev, mode, h.rho0, h.c, c->d_partial);
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(RED_BLOCK), 0, c->stream, c->d_partial, c->red_blocks,
+                       c->d_out);
+}
+
+int launch_reduce(lbfv_ctx *c, int mode) {
+    int st = ensure_reduction(c);
+    if (st) return st;
+    double ext[4];
+    current_ext(c->hc, ext);
+    switch (c->hc.variant) {
+    case V_F64: launch_reduce_t<double, double>(c, ext, mode); break;
+    case V_F32: launch_reduce_t<float, float>(c, ext, mode); break;
+    case V_BF16: launch_reduce_t<float, __bf16>(c, ext, mode); break;
+    default: launch_reduce_t<float, _Float16>(c, ext, mode); break;
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(c->h_out, c->d_out, sizeof(double) * RED_N, hipMemcpyDeviceToHost, c->stream));
+    return LBFV_OK;
+}
+
+// Examine a finished asynchronous check (wait for it when `wait`).
+int poll_check(lbfv_ctx *c, bool wait) {
+    if (!c->check_pending) return LBFV_OK;
+    if (wait) {
+        HIPCHK(hipEventSynchronize(c->check_event));
+    } else {
+        hipError_t q = hipEventQuery(c->check_event);
+        if (q == hipErrorNotReady) return LBFV_OK;
+        if (q != hipSuccess) return c->fail(LBFV_EHIP, std::string("hipEventQuery: ") + hipGetErrorString(q));
+    }
+    c->check_pending = false;
+    if (c->h_out[5] > 0) c->unstable = true;
+    return LBFV_OK;
+}
+
+int start_check(lbfv_ctx *c) {
+    int st = poll_check(c, true);
+    if (st) return st;
+    st = launch_reduce(c, 0);
+    if (st) return st;
+    HIPCHK(hipEventRecord(c->check_event, c->stream));
+    c->check_pending = true;
+    c->steps_at_check = c->steps;
+    return LBFV_OK;
+}
+
+int do_steps(lbfv_ctx *c, int scheme, int32_t n) {
+    if (!c) return LBFV_EINVAL;
+    if (n < 0) return c->fail(LBFV_EINVAL, "nsteps must be >= 0");
+    HostCase &h = c->hc;
+    if (!h.sides_set()) return c->fail(LBFV_ESTATE, "all four sides must be set before stepping");
+    if (!c->has_state) return c->fail(LBFV_ESTATE, "no initial state (init_equilibrium or set_f first)");
+    int st = poll_check(c, false);
+    if (st) return st;
+    if (c->unstable) return c->fail(LBFV_EUNSTABLE, "a non-finite value was found at a check");
+    double ext[4];
+    st = ensure_metrics(c, ext);
+    if (st) return st;
+    current_ext(h, ext);
+    if (c->rows <= 0) c->rows = default_rows(h, scheme, c->wpb);
+    while (n > 0) {
+        int seg = n;
+        if (c->check_every > 0) {
+            const int64_t to_check = c->check_every - (c->steps - c->steps_at_check);
+            seg = (int)std::min<int64_t>(seg, std::max<int64_t>(to_check, 1));
+        }
+        int left = seg;
+        while (left >= c->gsteps) {
+            hipGraphExec_t &g = c->gexec[scheme][h.cur];
+            if (!g) {
+                st = build_graph(c, scheme, h.cur, ext);
+                if (st) return st;
+            }
+            HIPCHK(hipGraphLaunch(g, c->stream));
+            h.cur ^= (c->gsteps & 1);
+            left -= c->gsteps;
+        }
+        for (; left > 0; --left) {
+            st = launch_one(c, scheme, h.cur, ext);
+            if (st) return st;
+            h.cur ^= 1;
+        }
+        c->steps += seg;
+        n -= seg;
+        if (c->check_every > 0 && c->steps - c->steps_at_check >= c->check_every) {
+            st = start_check(c);
+            if (st) return st;
+        }
+    }
+    return LBFV_OK;
+}
+
+template <typename T, typename S>
+int state_kernel_t(lbfv_ctx *c, int which, const double *d0, const double *d1, const double *d2, double *dout) {
+    HostCase &h = c->hc;
+    double ext[4];
+    current_ext(h, ext);
+    StepParams<T> P = make_params<T>(h, ext);
+    const int64_t n = (int64_t)h.nx * h.ny;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    switch (which) {
+    case 0: hipLaunchKernelGGL((init_eq_kernel<T, S>), dim3(blocks), dim3(256), 0, c->stream, P, h.cur, d0, d1, d2, 1.0 / h.c, h.rho0); break;
+    case 1: hipLaunchKernelGGL((set_f_kernel<T, S>), dim3(blocks), dim3(256), 0, c->stream, P, h.cur, d0, h.rho0); break;
+    case 2: hipLaunchKernelGGL((get_f_kernel<T, S>), dim3(blocks), dim3(256), 0, c->stream, P, h.cur, dout, h.rho0); break;
+    default: hipLaunchKernelGGL((moments_kernel<T, S>), dim3(blocks), dim3(256), 0, c->stream, P, h.cur, dout, dout + n, dout + 2 * n, h.rho0, h.c); break;
+    }
+    HIPCHK(hipGetLastError());
+    return LBFV_OK;
+}
+
+int state_kernel(lbfv_ctx *c, int which, const double *d0, const double *d1, const double *d2, double *dout) {
+    switch (c->hc.variant) {
+    case V_F64: return state_kernel_t<double, double>(c, which, d0, d1, d2, dout);
+    case V_F32: return state_kernel_t<float, float>(c, which, d0, d1, d2, dout);
+    case V_BF16: return state_kernel_t<float, __bf16>(c, which, d0, d1, d2, dout);
+    default: return state_kernel_t<float, _Float16>(c, which, d0, d1, d2, dout);
+    }
+}
+
+// device staging buffer of `count` doubles (freed by the caller)
+int staging(lbfv_ctx *c, size_t count, double **p) {
+    if (hipMalloc((void **)p, count * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return c->fail(LBFV_ENOMEM, "cannot allocate the staging buffer");
+    }
+    return LBFV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbfv_create(const lbfv_mesh *mesh, const lbfv_velset *vel, double tau, double dt, const lbfv_opts *opts,
+                lbfv_ctx **ctx) {
+    if (!ctx) {
+        g_last_error = "NULL ctx pointer";
+        return LBFV_EINVAL;
+    }
+    *ctx = nullptr;
+    lbfv_opts o = {LBFV_FP64, LBFV_STORE_NATIVE, 1.0, 1000, nullptr};
+    if (opts) o = *opts;
+    std::string msg;
+    int st = validate_case(mesh, vel, tau, dt, o.compute, o.storage, msg);
+    if (st) {
+        g_last_error = "lbfv_create: " + msg;
+        return st;
+    }
+    if (!(o.rho0 > 0) && o.storage != LBFV_STORE_NATIVE) {
+        g_last_error = "lbfv_create: rho0 must be > 0 for deviation storage";
+        return LBFV_EINVAL;
+    }
+    if (o.check_every < 0) {
+        g_last_error = "lbfv_create: check_every must be >= 0";
+        return LBFV_EINVAL;
+    }
+    lbfv_ctx *c = new (std::nothrow) lbfv_ctx();
+    if (!c) return LBFV_ENOMEM;
+    init_host_case(c->hc, mesh, vel, tau, dt, o.compute, o.storage, o.rho0);
+    c->check_every = o.check_every;
+    c->stream = (hipStream_t)o.hip_stream;
+    *ctx = c;
+    return LBFV_OK;
+}
+
+int lbfv_destroy(lbfv_ctx *c) {
+    if (!c) return LBFV_EINVAL;
+    (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    free_case(c->hc);
+    if (c->d_partial) (void)hipFree(c->d_partial);
+    if (c->d_out) (void)hipFree(c->d_out);
+    if (c->h_out) (void)hipHostFree(c->h_out);
+    if (c->d_uprev) (void)hipFree(c->d_uprev);
+    if (c->check_event) (void)hipEventDestroy(c->check_event);
+    delete c;
+    return LBFV_OK;
+}
+
+int lbfv_set_periodic(lbfv_ctx *c, int axis) {
+    if (!c) return LBFV_EINVAL;
+    if (axis != LBFV_X && axis != LBFV_Y) return c->fail(LBFV_EINVAL, "axis must be LBFV_X or LBFV_Y");
+    const int s0 = axis == LBFV_X ? SIDE_W : SIDE_S;
+    set_side(c->hc, s0, BC_PERIODIC, 0, 0, 0);
+    set_side(c->hc, s0 + 1, BC_PERIODIC, 0, 0, 0);
+    return LBFV_OK;
+}
+
+int lbfv_set_wall(lbfv_ctx *c, int side, double uwx, double uwy) {
+    if (!c) return LBFV_EINVAL;
+    if (side < 0 || side > 3 || !std::isfinite(uwx) || !std::isfinite(uwy))
+        return c->fail(LBFV_EINVAL, "lbfv_set_wall: bad side or velocity");
+    return set_side(c->hc, side, BC_WALL, uwx, uwy, 0);
+}
+
+int lbfv_set_inflow_eq(lbfv_ctx *c, int side, double rho, double ux, double uy) {
+    if (!c) return LBFV_EINVAL;
+    if (side < 0 || side > 3 || !(rho > 0) || !std::isfinite(ux) || !std::isfinite(uy))
+        return c->fail(LBFV_EINVAL, "lbfv_set_inflow_eq: bad side or state");
+    return set_side(c->hc, side, BC_INFLOW, rho, ux, uy);
+}
+
+int lbfv_set_outflow_extrap(lbfv_ctx *c, int side, int order) {
+    if (!c) return LBFV_EINVAL;
+    if (side < 0 || side > 3 || (order != 0 && order != 1))
+        return c->fail(LBFV_EINVAL, "lbfv_set_outflow_extrap: bad side or order");
+    return set_side(c->hc, side, BC_OUTFLOW, (double)order, 0, 0);
+}
+
+int lbfv_required_bytes(const lbfv_ctx *c, size_t *bytes) {
+    if (!c || !bytes) return LBFV_EINVAL;
+    *bytes = c->hc.buffer_bytes();
+    return LBFV_OK;
+}
+
+int lbfv_bind_buffers(lbfv_ctx *c, void *a, void *b, size_t bytes) {
+    if (!c) return LBFV_EINVAL;
+    if (!a || !b || a == b) return c->fail(LBFV_EINVAL, "lbfv_bind_buffers: two distinct buffers needed");
+    if (bytes < c->hc.buffer_bytes()) return c->fail(LBFV_EINVAL, "lbfv_bind_buffers: buffers too small");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HostCase &h = c->hc;
+    if (h.own) {
+        if (h.buf[0]) (void)hipFree(h.buf[0]);
+        if (h.buf[1]) (void)hipFree(h.buf[1]);
+    }
+    h.buf[0] = a;
+    h.buf[1] = b;
+    h.own = false;
+    h.cur = 0;
+    c->has_state = false;
+    drop_graphs(c);
+    HIPCHK(hipMemsetAsync(a, 0, h.buffer_bytes(), c->stream));
+    HIPCHK(hipMemsetAsync(b, 0, h.buffer_bytes(), c->stream));
+    return LBFV_OK;
+}
+
+int lbfv_init_equilibrium(lbfv_ctx *c, const double *rho, const double *ux, const double *uy) {
+    if (!c) return LBFV_EINVAL;
+    if (!rho || !ux || !uy) return c->fail(LBFV_EINVAL, "lbfv_init_equilibrium: NULL field");
+    int st = ensure_buffers(c);
+    if (st) return st;
+    HostCase &h = c->hc;
+    const int64_t n = (int64_t)h.nx * h.ny;
+    double *d;
+    st = staging(c, 3 * n, &d);
+    if (st) return st;
+    hipError_t e = hipMemcpyAsync(d, rho, n * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d + n, ux, n * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d + 2 * n, uy, n * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) {
+        st = state_kernel(c, 0, d, d + n, d + 2 * n, nullptr);
+        e = hipStreamSynchronize(c->stream);
+    }
+    (void)hipFree(d);
+    if (st) return st;
+    if (e != hipSuccess) return c->fail(LBFV_EHIP, std::string("init_equilibrium: ") + hipGetErrorString(e));
+    c->has_state = true;
+    c->unstable = false;
+    c->uprev_valid = false;
+    return LBFV_OK;
+}
+
+int lbfv_set_f(lbfv_ctx *c, const double *f) {
+    if (!c) return LBFV_EINVAL;
+    if (!f) return c->fail(LBFV_EINVAL, "lbfv_set_f: NULL array");
+    int st = ensure_buffers(c);
+    if (st) return st;
+    HostCase &h = c->hc;
+    const int64_t n = (int64_t)h.nx * h.ny;
+    double *d;
+    st = staging(c, 9 * n, &d);
+    if (st) return st;
+    hipError_t e = hipMemcpyAsync(d, f, 9 * n * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) {
+        st = state_kernel(c, 1, d, nullptr, nullptr, nullptr);
+        e = hipStreamSynchronize(c->stream);
+    }
+    (void)hipFree(d);
+    if (st) return st;
+    if (e != hipSuccess) return c->fail(LBFV_EHIP, std::string("set_f: ") + hipGetErrorString(e));
+    c->has_state = true;
+    c->unstable = false;
+    c->uprev_valid = false;
+    return LBFV_OK;
+}
+
+int lbfv_get_f(lbfv_ctx *c, double *f) {
+    if (!c) return LBFV_EINVAL;
+    if (!f) return c->fail(LBFV_EINVAL, "lbfv_get_f: NULL array");
+    if (!c->has_state) return c->fail(LBFV_ESTATE, "no state");
+    HostCase &h = c->hc;
+    const int64_t n = (int64_t)h.nx * h.ny;
+    double *d;
+    int st = staging(c, 9 * n, &d);
+    if (st) return st;
+    st = state_kernel(c, 2, nullptr, nullptr, nullptr, d);
+    hipError_t e = hipSuccess;
+    if (!st) e = hipMemcpyAsync(f, d, 9 * n * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(d);
+    if (st) return st;
+    if (e != hipSuccess) return c->fail(LBFV_EHIP, std::string("get_f: ") + hipGetErrorString(e));
+    return LBFV_OK;
+}
+
+int dugks_step(lbfv_ctx *c, int32_t n) { return do_steps(c, SCHEME_DUGKS, n); }
+int bkg_step(lbfv_ctx *c, int32_t n) { return do_steps(c, SCHEME_BKG, n); }
+
+int lbfv_moments(lbfv_ctx *c, double *rho, double *ux, double *uy) {
+    if (!c) return LBFV_EINVAL;
+    if (!rho || !ux || !uy) return c->fail(LBFV_EINVAL, "lbfv_moments: NULL output");
+    if (!c->has_state) return c->fail(LBFV_ESTATE, "no state");
+    HostCase &h = c->hc;
+    const int64_t n = (int64_t)h.nx * h.ny;
+    double *d;
+    int st = staging(c, 3 * n, &d);
+    if (st) return st;
+    st = state_kernel(c, 3, nullptr, nullptr, nullptr, d);
+    hipError_t e = hipSuccess;
+    if (!st) e = hipMemcpyAsync(rho, d, n * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ux, d + n, n * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(uy, d + 2 * n, n * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(d);
+    if (st) return st;
+    if (e != hipSuccess) return c->fail(LBFV_EHIP, std::string("moments: ") + hipGetErrorString(e));
+    return LBFV_OK;
+}
+
+int lbfv_totals(lbfv_ctx *c, double out[3]) {
+    if (!c) return LBFV_EINVAL;
+    if (!out) return c->fail(LBFV_EINVAL, "lbfv_totals: NULL output");
+    if (!c->has_state) return c->fail(LBFV_ESTATE, "no state");
+    int st = poll_check(c, true);
+    if (st) return st;
+    double ext[4];
+    st = ensure_metrics(c, ext);   // volumes come with the metric upload
+    if (st) return st;
+    st = launch_reduce(c, 0);
+    if (st) return st;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    out[0] = c->h_out[0];
+    out[1] = c->h_out[1];
+    out[2] = c->h_out[2];
+    if (c->h_out[5] > 0) c->unstable = true;
+    if (c->unstable) return c->fail(LBFV_EUNSTABLE, "a non-finite value was found");
+    return LBFV_OK;
+}
+
+int lbfv_residual(lbfv_ctx *c, double *r) {
+    if (!c) return LBFV_EINVAL;
+    if (!r) return c->fail(LBFV_EINVAL, "lbfv_residual: NULL output");
+    if (!c->has_state) return c->fail(LBFV_ESTATE, "no state");
+    double ext[4];
+    int st = ensure_metrics(c, ext);
+    if (st) return st;
+    st = poll_check(c, true);
+    if (st) return st;
+    const int64_t n = (int64_t)c->hc.nx * c->hc.ny;
+    if (!c->d_uprev) {
+        if (hipMalloc((void **)&c->d_uprev, sizeof(double) * 2 * n) != hipSuccess) {
+            (void)hipGetLastError();
+            return c->fail(LBFV_ENOMEM, "cannot allocate the residual buffer");
+        }
+        c->uprev_valid = false;
+    }
+    st = launch_reduce(c, 1);
+    if (st) return st;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->h_out[5] > 0) {
+        c->unstable = true;
+        return c->fail(LBFV_EUNSTABLE, "a non-finite value was found");
+    }
+    *r = c->uprev_valid ? std::sqrt(c->h_out[3] / c->h_out[4]) : 1.0;
+    c->uprev_valid = true;
+    return LBFV_OK;
+}
+
+int lbfv_set_tile(lbfv_ctx *c, int32_t rows, int32_t wpb) {
+    if (!c) return LBFV_EINVAL;
+    if (rows < 0 || (wpb != 0 && wpb != 1 && wpb != 2 && wpb != 4))
+        return c->fail(LBFV_EINVAL, "lbfv_set_tile: rows >= 1, waves per block 1, 2 or 4");
+    if (rows > 0) c->rows = rows;
+    if (wpb > 0) c->wpb = wpb;
+    drop_graphs(c);
+    return LBFV_OK;
+}
+
+int lbfv_get_tile(const lbfv_ctx *c, int32_t *rows, int32_t *wpb) {
+    if (!c || !rows || !wpb) return LBFV_EINVAL;
+    *rows = c->rows > 0 ? c->rows : default_rows(c->hc, SCHEME_DUGKS, c->wpb);
+    *wpb = c->wpb;
+    return LBFV_OK;
+}
+
+}  // extern "C"
+
+// ====================================================================== autotuner
+namespace {
+
+std::string arch_name() {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+    std::string a = p.gcnArchName;
+    return a.substr(0, a.find(':'));
+}
+
+int size_class(int n) {
+    int k = 0;
+    while ((1 << (k + 1)) <= n) ++k;
+    return k;
+}
+
+std::string tune_key(const HostCase &h, int scheme) {
+    std::ostringstream s;
+    s << arch_name() << " " << (scheme == SCHEME_DUGKS ? "dugks" : "bkg") << " v" << h.variant << " x"
+      << size_class(h.nx) << " y" << size_class(h.ny);
+    return s.str();
+}
+
+bool cache_lookup(const char *path, const std::string &key, int &rows, int &wpb, double &ms) {
+    if (!path) return false;
+    std::ifstream in(path);
+    std::string line;
+    bool found = false;
+    while (std::getline(in, line)) {
+        if (line.compare(0, key.size(), key) == 0 && line.size() > key.size() && line[key.size()] == '|') {
+            std::istringstream t(line.substr(key.size() + 1));
+            int r, w;
+            double m;
+            if (t >> r >> w >> m) {
+                rows = r;
+                wpb = w;
+                ms = m;
+                found = true;   // last entry wins
+            }
+        }
+    }
+    return found;
+}
+
+void cache_store(const char *path, const std::string &key, int rows, int wpb, double ms) {
+    if (!path) return;
+    std::ofstream out(path, std::ios::app);
+    out << key << "|" << rows << " " << wpb << " " << ms << "\n";
+}
+
+}  // namespace
+
+extern "C" int lbfv_autotune(lbfv_ctx *c, int scheme, int32_t trial_steps, const char *cache_path,
+                             double *best_ms) {
+    if (!c) return LBFV_EINVAL;
+    if (scheme != LBFV_DUGKS && scheme != LBFV_BKG) return c->fail(LBFV_EINVAL, "unknown scheme");
+    if (trial_steps < 1) return c->fail(LBFV_EINVAL, "trial_steps must be >= 1");
+    if (!c->has_state) return c->fail(LBFV_ESTATE, "autotune needs a state to step");
+    if (!c->hc.sides_set()) return c->fail(LBFV_ESTATE, "all four sides must be set");
+    const char *path = cache_path ? cache_path : getenv("LBFV_TUNE_CACHE");
+    HostCase &h = c->hc;
+    const std::string key = tune_key(h, scheme);
+    int rows, wpb;
+    double ms;
+    if (cache_lookup(path, key, rows, wpb, ms)) {
+        c->rows = std::min(rows, h.ny);
+        c->wpb = wpb;
+        drop_graphs(c);
+        if (best_ms) *best_ms = ms;
+        return LBFV_OK;
+    }
+    // save the state; trials step it
+    void *save = nullptr;
+    if (hipMalloc(&save, h.buffer_bytes()) != hipSuccess) {
+        (void)hipGetLastError();
+        return c->fail(LBFV_ENOMEM, "autotune: cannot allocate the save buffer");
+    }
+    const int saved_cur = h.cur;
+    const int64_t saved_steps = c->steps, saved_at = c->steps_at_check;
+    const int saved_check = c->check_every;
+    HIPCHK(hipMemcpyAsync(save, h.buf[h.cur], h.buffer_bytes(), hipMemcpyDeviceToDevice, c->stream));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    c->check_every = 0;
+    int best_r = 0, best_w = 0;
+    double best = INFINITY;
+    const int w_opts[] = {1, 2, 4};
+    int st = LBFV_OK;
+    std::vector<std::pair<int, int>> cands;
+    for (int w : w_opts) {
+        for (int r : {4, 8, 16, 32, 64, 128, 256})
+            if (r <= h.ny || r == 4) cands.push_back({std::min(r, h.ny), w});
+        for (int r : balanced_rows(h, resident_waves(step_fn_variant(h.variant, scheme, has_boundary(h)), w)))
+            cands.push_back({r, w});
+    }
+    std::sort(cands.begin(), cands.end());
+    cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
+    for (const auto &rw : cands) {
+        c->rows = rw.first;
+        c->wpb = rw.second;
+        drop_graphs(c);
+        if ((st = do_steps(c, scheme, 2))) break;   // warm-up
+        hipEventRecord(e0, c->stream);
+        if ((st = do_steps(c, scheme, trial_steps))) break;
+        hipEventRecord(e1, c->stream);
+        hipEventSynchronize(e1);
+        float t = 0;
+        hipEventElapsedTime(&t, e0, e1);
+        const double per = t / trial_steps;
+        if (per < best) {
+            best = per;
+            best_r = rw.first;
+            best_w = rw.second;
+        }
+    }
+    // restore
+    h.cur = saved_cur;
+    hipMemcpyAsync(h.buf[h.cur], save, h.buffer_bytes(), hipMemcpyDeviceToDevice, c->stream);
+    hipStreamSynchronize(c->stream);
+    hipFree(save);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    c->steps = saved_steps;
+    c->steps_at_check = saved_at;
+    c->check_every = saved_check;
+    if (st) return st;
+    c->rows = best_r;
+    c->wpb = best_w;
+    drop_graphs(c);
+    cache_store(path, key, best_r, best_w, best);
+    if (best_ms) *best_ms = best;
+    return LBFV_OK;
+}
+
+// ====================================================================== batch
+namespace {
+
+template <typename T>
+int batch_upload_params(lbfv_batch *b) {
+    std::vector<StepParams<T>> ps;
+    for (auto &h : b->cases) {
+        double ext[4];
+        current_ext(h, ext);
+        ps.push_back(make_params<T>(h, ext));
+    }
+    if (!b->d_params && hipMalloc(&b->d_params, ps.size() * sizeof(StepParams<T>)) != hipSuccess) {
+        (void)hipGetLastError();
+        return b->fail(LBFV_ENOMEM, "batch: cannot allocate the case table");
+    }
+    if (hipMemcpy(b->d_params, ps.data(), ps.size() * sizeof(StepParams<T>), hipMemcpyHostToDevice) != hipSuccess)
+        return b->fail(LBFV_EHIP, "batch: case table upload failed");
+    return LBFV_OK;
+}
+
+void batch_drop_graphs(lbfv_batch *b) {
+    for (auto &row : b->gexec)
+        for (auto &g : row)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+}
+
+int batch_build_items(lbfv_batch *b) {
+    std::vector<BatchItem> items;
+    // largest cases first so that the grid-stride walk ends on small items
+    std::vector<int> order(b->cases.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+        return (int64_t)b->cases[a].nx * b->cases[a].ny > (int64_t)b->cases[c].nx * b->cases[c].ny;
+    });
+    for (int ci : order) {
+        const HostCase &h = b->cases[ci];
+        const int rows = std::min(b->rows, h.ny);
+        for (int j0 = 0; j0 < h.ny; j0 += rows)
+            for (int x0 = 0; x0 < h.nx; x0 += 62) items.push_back({ci, x0, j0, std::min(h.ny, j0 + rows)});
+    }
+    if (b->d_items) (void)hipFree(b->d_items);
+    b->d_items = nullptr;
+    if (hipMalloc((void **)&b->d_items, items.size() * sizeof(BatchItem)) != hipSuccess) {
+        (void)hipGetLastError();
+        return b->fail(LBFV_ENOMEM, "batch: cannot allocate the work list");
+    }
+    if (hipMemcpy(b->d_items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice) != hipSuccess)
+        return b->fail(LBFV_EHIP, "batch: work list upload failed");
+    b->nitems = (int)items.size();
+    batch_drop_graphs(b);
+    return LBFV_OK;
+}
+
+struct BatchArgs {
+    const void *params;
+    const BatchItem *items;
+    int nitems, parity;
+    void *args[4];
+    void bind() {
+        args[0] = &params;
+        args[1] = &items;
+        args[2] = &nitems;
+        args[3] = &parity;
+    }
+};
+
+int batch_grid(const lbfv_batch *b) {
+    // persistent: at most 8 waves per CU resident on 256 CUs, 4 waves per block
+    return std::max(1, std::min((b->nitems + 3) / 4, 256 * 2));
+}
+
+int batch_launch_one(lbfv_batch *b, int scheme, int parity) {
+    BatchArgs a{b->d_params, b->d_items, b->nitems, parity};
+    a.bind();
+    hipError_t e = hipLaunchKernel(batch_fn_variant(b->variant, scheme, b->bnd), dim3(batch_grid(b)), dim3(256), a.args, 0,
+                                   b->stream);
+    if (e != hipSuccess) return b->fail(LBFV_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
+    return LBFV_OK;
+}
+
+int batch_build_graph(lbfv_batch *b, int scheme, int parity0) {
+    hipGraph_t g;
+    if (hipGraphCreate(&g, 0) != hipSuccess) return b->fail(LBFV_EHIP, "hipGraphCreate failed");
+    hipGraphNode_t prev = nullptr;
+    for (int s = 0; s < b->gsteps; ++s) {
+        BatchArgs a{b->d_params, b->d_items, b->nitems, (parity0 + s) & 1};
+        a.bind();
+        hipKernelNodeParams kp;
+        memset(&kp, 0, sizeof(kp));
+        kp.func = batch_fn_variant(b->variant, scheme, b->bnd);
+        kp.gridDim = dim3(batch_grid(b));
+        kp.blockDim = dim3(256);
+        kp.kernelParams = a.args;
+        hipGraphNode_t node;
+        hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return b->fail(LBFV_EHIP, std::string("hipGraphAddKernelNode: ") + hipGetErrorString(e));
+        }
+        prev = node;
+    }
+    hipError_t e = hipGraphInstantiate(&b->gexec[scheme][parity0], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return b->fail(LBFV_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    return LBFV_OK;
+}
+
+template <typename T, typename S>
+int batch_state_t(lbfv_batch *b, int ci, int which, const double *d0, const double *d1, const double *d2,
+                  double *dout) {
+    HostCase &h = b->cases[ci];
+    double ext[4];
+    current_ext(h, ext);
+    StepParams<T> P = make_params<T>(h, ext);
+    const int64_t n = (int64_t)h.nx * h.ny;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    switch (which) {
+    case 0: hipLaunchKernelGGL((init_eq_kernel<T, S>), dim3(blocks), dim3(256), 0, b->stream, P, b->parity, d0, d1, d2, 1.0 / h.c, h.rho0); break;
+    case 1: hipLaunchKernelGGL((set_f_kernel<T, S>), dim3(blocks), dim3(256), 0, b->stream, P, b->parity, d0, h.rho0); break;
+    case 2: hipLaunchKernelGGL((get_f_kernel<T, S>), dim3(blocks), dim3(256), 0, b->stream, P, b->parity, dout, h.rho0); break;
+    default: hipLaunchKernelGGL((moments_kernel<T, S>), dim3(blocks), dim3(256), 0, b->stream, P, b->parity, dout, dout + n, dout + 2 * n, h.rho0, h.c); break;
+    }
+    if (hipGetLastError() != hipSuccess) return b->fail(LBFV_EHIP, "batch state kernel launch failed");
+    return LBFV_OK;
+}
+
+int batch_state(lbfv_batch *b, int ci, int which, const double *d0, const double *d1, const double *d2, double *dout) {
+    switch (b->variant) {
+    case V_F64: return batch_state_t<double, double>(b, ci, which, d0, d1, d2, dout);
+    case V_F32: return batch_state_t<float, float>(b, ci, which, d0, d1, d2, dout);
+    case V_BF16: return batch_state_t<float, __bf16>(b, ci, which, d0, d1, d2, dout);
+    default: return batch_state_t<float, _Float16>(b, ci, which, d0, d1, d2, dout);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbfv_batch_create(int32_t n, const lbfv_case *cs, const lbfv_velset *vel, const lbfv_opts *opts,
+                      lbfv_batch **out) {
+    if (!out) {
+        g_last_error = "NULL batch pointer";
+        return LBFV_EINVAL;
+    }
+    *out = nullptr;
+    if (n < 1 || !cs) {
+        g_last_error = "lbfv_batch_create: need n >= 1 cases";
+        return LBFV_EINVAL;
+    }
+    lbfv_opts o = {LBFV_FP32, LBFV_STORE_DEV_FP32, 1.0, 0, nullptr};
+    if (opts) o = *opts;
+    std::string msg;
+    for (int i = 0; i < n; ++i) {
+        int st = validate_case(&cs[i].mesh, vel, cs[i].tau, cs[i].dt, o.compute, o.storage, msg);
+        if (st) {
+            g_last_error = "lbfv_batch_create: case " + std::to_string(i) + ": " + msg;
+            return st;
+        }
+        for (int s = 0; s < 4; ++s)
+            if (cs[i].bc_kind[s] < 0 || cs[i].bc_kind[s] > 3) {
+                g_last_error = "lbfv_batch_create: bad boundary kind";
+                return LBFV_EINVAL;
+            }
+        if ((cs[i].bc_kind[0] == BC_PERIODIC) != (cs[i].bc_kind[1] == BC_PERIODIC) ||
+            (cs[i].bc_kind[2] == BC_PERIODIC) != (cs[i].bc_kind[3] == BC_PERIODIC)) {
+            g_last_error = "lbfv_batch_create: a periodic axis needs both sides periodic";
+            return LBFV_EINVAL;
+        }
+    }
+    lbfv_batch *b = new (std::nothrow) lbfv_batch();
+    if (!b) return LBFV_ENOMEM;
+    b->stream = (hipStream_t)o.hip_stream;
+    b->cases.resize(n);
+    int st = LBFV_OK;
+    for (int i = 0; i < n && !st; ++i) {
+        HostCase &h = b->cases[i];
+        init_host_case(h, &cs[i].mesh, vel, cs[i].tau, cs[i].dt, o.compute, o.storage, o.rho0);
+        for (int s = 0; s < 4; ++s) {
+            h.bc[s] = cs[i].bc_kind[s];
+            for (int q = 0; q < 3; ++q) h.bcval[s][q] = cs[i].bc_val[s][q];
+        }
+        b->variant = h.variant;
+        double ext[4];
+        if (hipMalloc(&h.buf[0], h.buffer_bytes()) != hipSuccess || hipMalloc(&h.buf[1], h.buffer_bytes()) != hipSuccess) {
+            (void)hipGetLastError();
+            st = b->fail(LBFV_ENOMEM, "batch: cannot allocate case buffers");
+            break;
+        }
+        (void)hipMemset(h.buf[0], 0, h.buffer_bytes());
+        (void)hipMemset(h.buf[1], 0, h.buffer_bytes());
+        if (upload_metrics(h, ext, b->stream) != hipSuccess) st = b->fail(LBFV_EHIP, "batch: metric upload failed");
+    }
+    for (auto &h : b->cases) b->bnd = b->bnd || has_boundary(h);
+    if (!st) st = is_f64(b->variant) ? batch_upload_params<double>(b) : batch_upload_params<float>(b);
+    if (!st) st = batch_build_items(b);
+    if (st) {
+        lbfv_batch_destroy(b);
+        return st;
+    }
+    *out = b;
+    return LBFV_OK;
+}
+
+int lbfv_batch_destroy(lbfv_batch *b) {
+    if (!b) return LBFV_EINVAL;
+    (void)hipStreamSynchronize(b->stream);
+    batch_drop_graphs(b);
+    for (auto &h : b->cases) free_case(h);
+    if (b->d_params) (void)hipFree(b->d_params);
+    if (b->d_items) (void)hipFree(b->d_items);
+    delete b;
+    return LBFV_OK;
+}
+
+int lbfv_batch_set_shape(lbfv_batch *b, int32_t graph_steps, int32_t rows) {
+    if (!b) return LBFV_EINVAL;
+    if (graph_steps < 0 || rows < 0) return b->fail(LBFV_EINVAL, "bad shape");
+    if (graph_steps > 0) b->gsteps = graph_steps;
+    batch_drop_graphs(b);
+    if (rows > 0 && rows != b->rows) {
+        b->rows = rows;
+        return batch_build_items(b);
+    }
+    return LBFV_OK;
+}
+
+int lbfv_batch_info(const lbfv_batch *b, int64_t *cells, int32_t *items) {
+    if (!b) return LBFV_EINVAL;
+    int64_t t = 0;
+    for (auto &h : b->cases) t += (int64_t)h.nx * h.ny;
+    if (cells) *cells = t;
+    if (items) *items = b->nitems;
+    return LBFV_OK;
+}
+
+int lbfv_batch_init_equilibrium(lbfv_batch *b, int32_t ci, const double *rho, const double *ux, const double *uy) {
+    if (!b) return LBFV_EINVAL;
+    if (ci < 0 || ci >= (int)b->cases.size() || !rho || !ux || !uy) return b->fail(LBFV_EINVAL, "bad case or field");
+    HostCase &h = b->cases[ci];
+    const int64_t n = (int64_t)h.nx * h.ny;
+    double *d;
+    if (hipMalloc((void **)&d, 3 * n * 8) != hipSuccess) {
+        (void)hipGetLastError();
+        return b->fail(LBFV_ENOMEM, "staging");
+    }
+    hipMemcpyAsync(d, rho, n * 8, hipMemcpyHostToDevice, b->stream);
+    hipMemcpyAsync(d + n, ux, n * 8, hipMemcpyHostToDevice, b->stream);
+    hipMemcpyAsync(d + 2 * n, uy, n * 8, hipMemcpyHostToDevice, b->stream);
+    int st = batch_state(b, ci, 0, d, d + n, d + 2 * n, nullptr);
+    hipError_t e = hipStreamSynchronize(b->stream);
+    hipFree(d);
+    if (st) return st;
+    if (e != hipSuccess) return b->fail(LBFV_EHIP, hipGetErrorString(e));
+    return LBFV_OK;
+}
+
+int lbfv_batch_set_f(lbfv_batch *b, int32_t ci, const double *f) {
+    if (!b) return LBFV_EINVAL;
+    if (ci < 0 || ci >= (int)b->cases.size() || !f) return b->fail(LBFV_EINVAL, "bad case or array");
+    HostCase &h = b->cases[ci];
+    const int64_t n = (int64_t)h.nx * h.ny;
+    double *d;
+    if (hipMalloc((void **)&d, 9 * n * 8) != hipSuccess) {
+        (void)hipGetLastError();
+        return b->fail(LBFV_ENOMEM, "staging");
+    }
+    hipMemcpyAsync(d, f, 9 * n * 8, hipMemcpyHostToDevice, b->stream);
+    int st = batch_state(b, ci, 1, d, nullptr, nullptr, nullptr);
+    hipError_t e = hipStreamSynchronize(b->stream);
+    hipFree(d);
+    if (st) return st;
+    if (e != hipSuccess) return b->fail(LBFV_EHIP, hipGetErrorString(e));
+    return LBFV_OK;
+}
+
+static int batch_fetch(lbfv_batch *b, int32_t ci, int which, double *out, int64_t count) {
+    double *d;
+    if (hipMalloc((void **)&d, count * 8) != hipSuccess) {
+        (void)hipGetLastError();
+        return b->fail(LBFV_ENOMEM, "staging");
+    }
+    int st = batch_state(b, ci, which, nullptr, nullptr, nullptr, d);
+    hipError_t e = hipSuccess;
+    if (!st) e = hipMemcpyAsync(out, d, count * 8, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    hipFree(d);
+    if (st) return st;
+    if (e != hipSuccess) return b->fail(LBFV_EHIP, hipGetErrorString(e));
+    return LBFV_OK;
+}
+
+int lbfv_batch_get_f(lbfv_batch *b, int32_t ci, double *f) {
+    if (!b) return LBFV_EINVAL;
+    if (ci < 0 || ci >= (int)b->cases.size() || !f) return b->fail(LBFV_EINVAL, "bad case or array");
+    const HostCase &h = b->cases[ci];
+    return batch_fetch(b, ci, 2, f, 9 * (int64_t)h.nx * h.ny);
+}
+
+int lbfv_batch_moments(lbfv_batch *b, int32_t ci, double *rho, double *ux, double *uy) {
+    if (!b) return LBFV_EINVAL;
+    if (ci < 0 || ci >= (int)b->cases.size() || !rho || !ux || !uy) return b->fail(LBFV_EINVAL, "bad case or output");
+    const HostCase &h = b->cases[ci];
+    const int64_t n = (int64_t)h.nx * h.ny;
+    std::vector<double> tmp(3 * n);
+    int st = batch_fetch(b, ci, 3, tmp.data(), 3 * n);
+    if (st) return st;
+    memcpy(rho, tmp.data(), n * 8);
+    memcpy(ux, tmp.data() + n, n * 8);
+    memcpy(uy, tmp.data() + 2 * n, n * 8);
+    return LBFV_OK;
+}
+
+int lbfv_batch_step(lbfv_batch *b, int scheme, int32_t n) {
+    if (!b) return LBFV_EINVAL;
+    if (scheme != LBFV_DUGKS && scheme != LBFV_BKG) return b->fail(LBFV_EINVAL, "unknown scheme");
+    if (n < 0) return b->fail(LBFV_EINVAL, "nsteps must be >= 0");
+    while (n >= b->gsteps) {
+        hipGraphExec_t &g = b->gexec[scheme][b->parity];
+        if (!g) {
+            int st = batch_build_graph(b, scheme, b->parity);
+            if (st) return st;
+        }
+        hipError_t e = hipGraphLaunch(g, b->stream);
+        if (e != hipSuccess) return b->fail(LBFV_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+        b->parity ^= (b->gsteps & 1);
+        n -= b->gsteps;
+    }
+    for (; n > 0; --n) {
+        int st = batch_launch_one(b, scheme, b->parity);
+        if (st) return st;
+        b->parity ^= 1;
+    }
+    return LBFV_OK;
+}
+
+}  // extern "C"

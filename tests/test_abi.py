@@ -1,0 +1,112 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function the
+header declares, validates arguments before touching the device, and its host
+helpers agree with the oracle."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1511_00242_amd import inputs as I
+from paper_1511_00242_amd import lbfv as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbfv.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_function():
+    names = header_functions()
+    assert "lbfv_create" in names and "dugks_step" in names and "bkg_step" in names
+    lib = L.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.EXPORTS)
+
+
+def test_strerror_covers_every_status():
+    for s in range(0, -7, -1):
+        assert L.lib().lbfv_strerror(s) not in (b"", b"unknown status")
+
+
+def _mesh(nx=8, ny=6):
+    return I.uniform_faces(nx), I.uniform_faces(ny)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=1), dict(ny=1), dict(tau=0.0), dict(tau=-1.0), dict(dt=0.0), dict(rt=0.0),
+    dict(q=19), dict(nonmono=True), dict(compute=0, storage=2), dict(compute=0, storage=1),
+    dict(compute=7),
+])
+def test_create_rejects_bad_arguments(bad):
+    nx, ny = bad.get("nx", 8), bad.get("ny", 6)
+    xf, yf = I.uniform_faces(nx), I.uniform_faces(ny)
+    if bad.get("nonmono"):
+        xf = xf.copy(); xf[3] = xf[2]
+    m = L._Mesh(nx, ny, L._p(xf), L._p(yf))
+    v = L._Velset(bad.get("q", 9), bad.get("rt", 1 / 3))
+    o = L._Opts(bad.get("compute", 0), bad.get("storage", 0), 1.0, 100, None)
+    h = C.c_void_p()
+    st = L.lib().lbfv_create(C.byref(m), C.byref(v), bad.get("tau", 0.1), bad.get("dt", 0.01),
+                             C.byref(o), C.byref(h))
+    assert st == L.LBFV_EINVAL
+    assert not h.value
+    assert L.lib().lbfv_last_error(None)
+
+
+def test_null_pointers_are_rejected():
+    lib = L.lib()
+    assert lib.lbfv_create(None, None, 0.1, 0.1, None, None) == L.LBFV_EINVAL
+    assert lib.lbfv_destroy(None) == L.LBFV_EINVAL
+    assert lib.dugks_step(None, 1) == L.LBFV_EINVAL
+    assert lib.bkg_step(None, 1) == L.LBFV_EINVAL
+    assert lib.lbfv_batch_create(0, None, None, None, None) == L.LBFV_EINVAL
+
+
+def test_state_errors_before_any_device_work():
+    xf, yf = _mesh()
+    ctx = L.Context(xf, yf, 0.1, 0.01)
+    # sides unset -> ESTATE
+    assert L.lib().dugks_step(ctx.h, 1) == L.LBFV_ESTATE
+    ctx.set_sides(["periodic"] * 4)
+    # no state -> ESTATE
+    assert L.lib().bkg_step(ctx.h, 1) == L.LBFV_ESTATE
+    with pytest.raises(L.LbfvError) as e:
+        ctx.dugks_step(1)
+    assert e.value.status == L.LBFV_ESTATE
+    # bad setter arguments
+    assert L.lib().lbfv_set_wall(ctx.h, 7, 0.0, 0.0) == L.LBFV_EINVAL
+    assert L.lib().lbfv_set_outflow_extrap(ctx.h, 0, 2) == L.LBFV_EINVAL
+    assert L.lib().lbfv_set_inflow_eq(ctx.h, 0, -1.0, 0.0, 0.0) == L.LBFV_EINVAL
+    assert L.lib().lbfv_set_periodic(ctx.h, 5) == L.LBFV_EINVAL
+    assert L.lib().lbfv_set_tile(ctx.h, 8, 3) == L.LBFV_EINVAL
+    assert L.lib().dugks_step(ctx.h, -1) == L.LBFV_EINVAL
+    # replacing one side of a periodic axis leaves the other side unset
+    L._check(L.lib().lbfv_set_wall(ctx.h, L.LBFV_WEST, 0.0, 0.0), ctx.h)
+    assert L.lib().dugks_step(ctx.h, 1) == L.LBFV_ESTATE
+    ctx.close()
+
+
+def test_required_bytes_layout():
+    xf, yf = I.uniform_faces(100), I.uniform_faces(7)
+    for compute, storage, esize in ((0, 0, 8), (1, 0, 4), (1, 1, 4), (1, 2, 2), (1, 3, 2)):
+        ctx = L.Context(xf, yf, 0.1, 0.01, compute=compute, storage=storage)
+        assert ctx.required_bytes() == 9 * 7 * 128 * esize   # rows padded to 64 elements
+        ctx.close()
+
+
+def test_dt_from_cfl_matches_oracle():
+    from oracle import oracle as O
+    for xf, yf in ((I.uniform_faces(32, 0, 6.28), I.uniform_faces(32, 0, 6.28)),
+                   (I.tanh_faces(40, 2.0), I.geometric_faces(30, 0.01, 2.0))):
+        for cfl in (0.5, 1.1):
+            assert L.dt_from_cfl(xf, yf, 1 / 3, cfl) == pytest.approx(O.dt_from_cfl(xf, yf, 1 / 3, cfl),
+                                                                       rel=1e-15)
+    with pytest.raises(L.LbfvError):
+        L.dt_from_cfl(xf, yf, -1.0, 0.5)

@@ -1,0 +1,319 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle.
+
+Bars: FP64 relative L2 <= 1e-12 on f~ (all 9 directions) and on u; FP32
+deviation storage <= 1e-5 on u.  Relative L2: ||X_gpu - X_oracle|| / ||X_oracle||
+over all cells.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1511_00242_amd import inputs as I
+from paper_1511_00242_amd import lbfv as L
+
+pytestmark = pytest.mark.gpu
+THREADS = int(os.environ.get("LBFV_ORACLE_THREADS", "8"))
+TOL64 = 1e-12
+TOL32_U = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    torch.cuda.set_device(0)
+    yield
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def u_rel(ora, fa, fb):
+    _, ua, va = ora.moments(fa)
+    _, ub, vb = ora.moments(fb)
+    return rel(np.stack([ua, va]), np.stack([ub, vb]))
+
+
+def oracle_case(w, threads=THREADS):
+    return O.Case(w.xf, w.yf, w.rt, w.tau, w.dt, w.bcs, threads=threads)
+
+
+def gpu_run(w, scheme, nsteps, f0=None, tile=None, **kw):
+    with L.Context(w.xf, w.yf, w.tau, w.dt, rt=w.rt, bcs=w.bcs, **kw) as ctx:
+        if tile:
+            ctx.set_tile(*tile)
+        if f0 is None:
+            ctx.init_equilibrium(w.rho, w.ux, w.uy)
+        else:
+            ctx.set_f(f0)
+        ctx.step(scheme, nsteps)
+        return ctx.get_f()
+
+
+def perturbed_state(ora, w, seed, amp=1e-3):
+    f = ora.init_equilibrium(w.rho, w.ux, w.uy)
+    rng = np.random.default_rng(seed)
+    wts = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)[:, None, None]
+    return f + amp * wts * (rng.random(f.shape) - 0.5)
+
+
+SCHEMES = [(L.LBFV_DUGKS, O.DUGKS), (L.LBFV_BKG, O.BKG)]
+
+
+# ------------------------------------------------------------------ FP64 parity
+@pytest.mark.parametrize("scheme,oscheme", SCHEMES)
+def test_taylor_green_32_fp64(scheme, oscheme):
+    w = I.taylor_green(32)
+    ora = oracle_case(w, 1)
+    f0 = ora.init_equilibrium(w.rho, w.ux, w.uy)
+    ref = ora.run(f0, oscheme, 1000)
+    g = gpu_run(w, scheme, 1000)
+    print(f"tg32 scheme={scheme} f {rel(g, ref):.2e} u {u_rel(ora, g, ref):.2e}")
+    assert rel(g, ref) < TOL64
+    assert u_rel(ora, g, ref) < TOL64
+
+
+def _mixed_workload(nx=130, ny=37):
+    xf = I.tanh_faces(nx, 1.4, 0.0, 2.0)
+    yf = I.geometric_faces(ny, 0.01, 1.0)
+    shape = (ny, nx)
+    rho, ux, uy = I.random_state_fields(ny, nx, 5, amp_u=0.04, amp_rho=0.02)
+    return I.Workload("mixed", xf, yf, 0.004, I.cfl_dt(xf, yf, 0.6),
+                      [("inflow", 1.01, 0.03, -0.01), ("outflow", 1), ("wall", 0.02, 0.0), ("outflow", 0)],
+                      rho, ux, uy)
+
+
+@pytest.mark.parametrize("scheme,oscheme", SCHEMES)
+def test_ragged_mixed_boundaries_all_tiles(scheme, oscheme):
+    """130 x 37 cells (three x-strips, the last ragged), stretched both ways, all four
+    boundary kinds; every launch shape gives the same bits and matches the oracle."""
+    w = _mixed_workload()
+    ora = oracle_case(w)
+    f0 = perturbed_state(ora, w, 3)
+    ref = ora.run(f0, oscheme, 40)
+    outs = []
+    for tile in ((4, 1), (7, 2), (16, 4), (37, 4), (64, 1)):
+        g = gpu_run(w, scheme, 40, f0, tile=tile)
+        print(f"mixed scheme={scheme} tile={tile} f {rel(g, ref):.2e}")
+        assert rel(g, ref) < TOL64
+        outs.append(g)
+    for g in outs[1:]:
+        assert np.array_equal(g, outs[0])
+
+
+EDGE_SIZES = [(2, 2), (3, 5), (61, 3), (62, 4), (63, 2), (124, 3), (125, 6), (200, 2)]
+
+
+@pytest.mark.parametrize("nx,ny", EDGE_SIZES)
+def test_edge_sizes(nx, ny):
+    xf = I.uniform_faces(nx, 0.0, nx / 8.0)
+    yf = I.tanh_faces(ny, 0.7, 0.0, ny / 8.0)
+    rho, ux, uy = I.random_state_fields(ny, nx, nx * 100 + ny)
+    for bcs in (["periodic"] * 4,
+                [("wall", 0.0, 0.01), ("wall", 0.0, -0.01), ("wall", 0.02, 0.0), ("wall", -0.01, 0.0)],
+                ["periodic", "periodic", ("wall", 0.0, 0.0), ("inflow", 1.0, 0.02, 0.0)],
+                [("inflow", 1.0, 0.02, 0.0), ("outflow", 0), "periodic", "periodic"]):
+        w = I.Workload("edge", xf, yf, 0.01, I.cfl_dt(xf, yf, 0.5), bcs, rho, ux, uy)
+        ora = oracle_case(w, 1)
+        f0 = perturbed_state(ora, w, 7)
+        for scheme, oscheme in SCHEMES:
+            ref = ora.run(f0, oscheme, 12)
+            g = gpu_run(w, scheme, 12, f0, tile=(3, 2))
+            assert rel(g, ref) < TOL64, (nx, ny, bcs, scheme)
+
+
+@pytest.mark.parametrize("scheme,oscheme", SCHEMES)
+def test_cavity_256_tanh_fp64(scheme, oscheme):
+    """Lid-driven cavity mesh as run by the workload: 256^2, tanh with largest
+    adjacent ratio 1.05, U_lid 0.1, Re 1000; 300 steps from rest."""
+    w = I.cavity(256)
+    ora = oracle_case(w)
+    f0 = ora.init_equilibrium(w.rho, w.ux, w.uy)
+    ref = ora.run(f0, oscheme, 300)
+    g = gpu_run(w, scheme, 300)
+    print(f"cavity256 scheme={scheme} f {rel(g, ref):.2e} u {u_rel(ora, g, ref):.2e}")
+    assert rel(g, ref) < TOL64
+    assert u_rel(ora, g, ref) < TOL64
+
+
+@pytest.mark.parametrize("scheme,oscheme", SCHEMES)
+def test_boundary_layer_512x256_fp64(scheme, oscheme):
+    w = I.boundary_layer()
+    ora = oracle_case(w)
+    f0 = ora.init_equilibrium(w.rho, w.ux, w.uy)
+    ref = ora.run(f0, oscheme, 150)
+    g = gpu_run(w, scheme, 150)
+    print(f"bl scheme={scheme} f {rel(g, ref):.2e} u {u_rel(ora, g, ref):.2e}")
+    assert rel(g, ref) < TOL64
+    assert u_rel(ora, g, ref) < TOL64
+
+
+# ------------------------------------------------------------------ reduced precision
+@pytest.mark.parametrize("scheme,oscheme", SCHEMES)
+def test_fp32_deviation_storage_tg32(scheme, oscheme):
+    w = I.taylor_green(32)
+    ora = oracle_case(w, 1)
+    f0 = ora.init_equilibrium(w.rho, w.ux, w.uy)
+    ref = ora.run(f0, oscheme, 1000)
+    g = gpu_run(w, scheme, 1000, compute=L.LBFV_FP32, storage=L.LBFV_STORE_DEV_FP32)
+    e = u_rel(ora, g, ref)
+    print(f"fp32 dev scheme={scheme} u {e:.2e}")
+    assert e < TOL32_U
+
+
+@pytest.mark.parametrize("storage,bound", [(L.LBFV_STORE_DEV_BF16, 0.2), (L.LBFV_STORE_DEV_FP16, 0.05)])
+def test_16bit_storage_reports_error(storage, bound):
+    """16-bit deviation storage: FP32 arithmetic, error reported against the oracle
+    (rounding of the stored deviation limits it; the bound only catches breakage)."""
+    w = I.taylor_green(32)
+    ora = oracle_case(w, 1)
+    f0 = ora.init_equilibrium(w.rho, w.ux, w.uy)
+    ref = ora.run(f0, O.DUGKS, 200)
+    g = gpu_run(w, L.LBFV_DUGKS, 200, compute=L.LBFV_FP32, storage=storage)
+    e = u_rel(ora, g, ref)
+    print(f"16-bit storage={storage} u {e:.2e}")
+    assert e < bound
+
+
+# ------------------------------------------------------------------ observables and control
+def test_moments_totals_residual():
+    w = _mixed_workload(90, 40)
+    ora = oracle_case(w)
+    f0 = perturbed_state(ora, w, 11)
+    with L.Context(w.xf, w.yf, w.tau, w.dt, bcs=w.bcs) as ctx:
+        ctx.set_f(f0)
+        assert np.array_equal(ctx.get_f(), f0)
+        r, u, v = ctx.moments()
+        ro, uo, vo = ora.moments(f0)
+        assert rel(r, ro) < 1e-15 and rel(u, uo) < 1e-14 and rel(v, vo) < 1e-14
+        t = ctx.totals()
+        to = ora.totals(f0)
+        assert abs(t[0] - to[0]) / to[0] < 1e-14
+        assert np.max(np.abs(t[1:] - to[1:])) / to[0] < 1e-14
+        assert ctx.residual() == 1.0            # first call: no previous velocity
+        assert ctx.residual() == 0.0            # unchanged state
+        ctx.dugks_step(5)
+        res = ctx.residual()
+        f5 = ora.run(f0, O.DUGKS, 5)
+        _, u5, v5 = ora.moments(f5)
+        expect = math.sqrt(((u5 - uo) ** 2 + (v5 - vo) ** 2).sum() / (u5 ** 2 + v5 ** 2).sum())
+        assert res == pytest.approx(expect, rel=1e-9)
+
+
+def test_nonfinite_value_gives_unstable():
+    w = I.taylor_green(16)
+    with L.Context(w.xf, w.yf, w.tau, w.dt, bcs=w.bcs, check_every=1) as ctx:
+        ctx.init_equilibrium(w.rho, w.ux, w.uy)
+        f = ctx.get_f()
+        f[3, 5, 7] = np.nan
+        ctx.set_f(f)
+        ctx.dugks_step(1)                       # the check after this step sees the NaN
+        with pytest.raises(L.LbfvError) as e:
+            ctx.dugks_step(1)
+        assert e.value.status == L.LBFV_EUNSTABLE
+        with pytest.raises(L.LbfvError) as e:
+            ctx.totals()
+        assert e.value.status == L.LBFV_EUNSTABLE
+
+
+def test_graph_replay_equals_single_launches_and_is_deterministic():
+    w = _mixed_workload(70, 33)
+    ora = oracle_case(w)
+    f0 = perturbed_state(ora, w, 13)
+    outs = []
+    for mode in ("graph", "single", "graph"):
+        with L.Context(w.xf, w.yf, w.tau, w.dt, bcs=w.bcs) as ctx:
+            ctx.set_f(f0)
+            if mode == "graph":
+                ctx.dugks_step(70)              # two 32-step graph replays + 6 launches
+            else:
+                for _ in range(70):
+                    ctx.dugks_step(1)
+            outs.append(ctx.get_f())
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    assert rel(outs[0], ora.run(f0, O.DUGKS, 70)) < TOL64
+
+
+def test_torch_buffers_and_stream():
+    import torch
+    w = I.taylor_green(48)
+    ora = oracle_case(w, 1)
+    f0 = ora.init_equilibrium(w.rho, w.ux, w.uy)
+    s = torch.cuda.Stream()
+    with L.Context(w.xf, w.yf, w.tau, w.dt, bcs=w.bcs, stream=s.cuda_stream) as ctx:
+        ctx.bind_torch_buffers()
+        ctx.init_equilibrium(w.rho, w.ux, w.uy)
+        ctx.bkg_step(100)
+        g = ctx.get_f()
+    assert rel(g, ora.run(f0, O.BKG, 100)) < TOL64
+
+
+def test_autotune_keeps_state(tmp_path):
+    w = _mixed_workload(150, 60)
+    ora = oracle_case(w)
+    f0 = perturbed_state(ora, w, 17)
+    cache = str(tmp_path / "tune.txt")
+    with L.Context(w.xf, w.yf, w.tau, w.dt, bcs=w.bcs) as ctx:
+        ctx.set_f(f0)
+        ms = ctx.autotune(L.LBFV_DUGKS, 5, cache)
+        assert ms > 0
+        assert np.array_equal(ctx.get_f(), f0)
+        ctx.dugks_step(10)
+        g = ctx.get_f()
+        tile = ctx.get_tile()
+    assert rel(g, ora.run(f0, O.DUGKS, 10)) < TOL64
+    assert open(cache).read().count("|") == 1
+    with L.Context(w.xf, w.yf, w.tau, w.dt, bcs=w.bcs) as ctx:   # cached: no timing
+        ctx.set_f(f0)
+        ctx.autotune(L.LBFV_DUGKS, 5, cache)
+        assert ctx.get_tile() == tile
+
+
+# ------------------------------------------------------------------ batched form
+def _small_batch():
+    cases = [I.taylor_green(40, nu=0.02), I.cavity(33, re=200.0, stretched=False),
+             _mixed_workload(75, 21), I.taylor_green(64, nu=0.005)]
+    return cases
+
+
+@pytest.mark.parametrize("compute,storage,tol", [(L.LBFV_FP64, L.LBFV_STORE_NATIVE, TOL64),
+                                                 (L.LBFV_FP32, L.LBFV_STORE_DEV_FP32, TOL32_U)])
+def test_batch_matches_oracle_per_case(compute, storage, tol):
+    cases = _small_batch()
+    b = L.Batch(cases, compute=compute, storage=storage)
+    b.set_shape(graph_steps=10, rows=8)
+    refs = []
+    for i, w in enumerate(cases):
+        ora = oracle_case(w, 2)
+        f0 = ora.init_equilibrium(w.rho, w.ux, w.uy)
+        b.set_f(i, f0)
+        refs.append((ora, ora.run(f0, O.DUGKS, 25)))
+    b.step(L.LBFV_DUGKS, 25)                    # two graph replays + 5 launches
+    for i, (ora, ref) in enumerate(refs):
+        g = b.get_f(i)
+        e = u_rel(ora, g, ref)
+        print(f"batch case {i} compute={compute} u {e:.2e} f {rel(g, ref):.2e}")
+        assert e < tol
+        if compute == L.LBFV_FP64:
+            assert rel(g, ref) < TOL64
+    b.close()
+
+
+# ------------------------------------------------------------------ full-size workload
+@pytest.mark.parametrize("scheme,oscheme", SCHEMES)
+def test_taylor_green_4096_fp64_bench_shape(scheme, oscheme):
+    """The benchmark's workload (4096^2, default launch shape) for two steps, every
+    cell compared with the oracle."""
+    w = I.taylor_green(4096)
+    ora = oracle_case(w, 16)
+    f0 = ora.init_equilibrium(w.rho, w.ux, w.uy)
+    ref = ora.run(f0, oscheme, 2)
+    g = gpu_run(w, scheme, 2)
+    e = rel(g - f0, ref - f0)
+    print(f"tg4096 scheme={scheme} f {rel(g, ref):.2e} increment {e:.2e}")
+    assert rel(g, ref) < TOL64
+    assert e < 1e-9     # the 2-step increment itself, relative
