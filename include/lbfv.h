@@ -113,6 +113,11 @@ int lbfv_set_outflow_extrap(lbfv_ctx *ctx, int side, int order);
 
 /* State.  f~ of an equilibrium state is feq (Omega(feq) = 0). */
 int lbfv_init_equilibrium(lbfv_ctx *ctx, const double *rho, const double *ux, const double *uy);
+/* Chapman-Enskog initial state (Sec. 3.1): f = feq - tau (d_t feq + xi.grad feq) evaluated
+ * from rho, u and their derivatives by the chain rule, stored as f~ = f - (dt/2) Omega(f).
+ * drho, dux, duy: [3][ny][nx] FP64, the derivatives along (t, x, y). */
+int lbfv_init_chapman_enskog(lbfv_ctx *ctx, const double *rho, const double *ux, const double *uy,
+                             const double *drho, const double *dux, const double *duy);
 int lbfv_set_f(lbfv_ctx *ctx, const double *f);   /* f~, [9][ny][nx] FP64 */
 int lbfv_get_f(lbfv_ctx *ctx, double *f);         /* f~, [9][ny][nx] FP64 */
 /* Use caller-owned device buffers (e.g. PyTorch tensors) for the two state buffers;

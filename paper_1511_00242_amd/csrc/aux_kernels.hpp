@@ -9,7 +9,7 @@ namespace lbfv {
 template <typename T>
 __device__ __forceinline__ int64_t cell_offset(const StepParams<T> &P, int64_t k) {
     const int64_t j = k / P.nx, i = k - j * P.nx;
-    return j * P.pitch + i;
+    return j * P.pitch + col_slot((int)i);
 }
 
 // f~ of an equilibrium state (Omega(feq) = 0): x_a = w_a (rho - rho0 + rho P_a(u / c)),
@@ -27,6 +27,38 @@ __global__ void init_eq_kernel(StepParams<T> P, int parity, const double *rho, c
         for (int a = 0; a < 9; ++a) {
             const double x = dfeq<double>(a, r - rho0, r, r * u, r * v, u, v, usq15);
             p[a * P.plane] = Storage<S>::store((T)x, a);
+        }
+    }
+}
+
+// Chapman-Enskog initial state of Sec. 3.1: f = feq - tau (d_t feq + xi.grad feq), with the
+// derivatives of feq by the chain rule from the derivative fields of rho and u (each given
+// as [3][ny][nx] along t, x, y), then stored as f~ = f + (dt / 2 tau)(f - feq) (Sec. 2.2).
+// Evaluated in FP64 and rounded once to the stored type.
+template <typename T, typename S>
+__global__ void init_ce_kernel(StepParams<T> P, int parity, const double *rho, const double *ux, const double *uy,
+                               const double *drho, const double *dux, const double *duy, double c, double tau,
+                               double dt, double rho0) {
+    const int64_t n = (int64_t)P.nx * P.ny;
+    S *dst = (S *)P.buf[parity];
+    const double inv_c = 1.0 / c, k = 0.5 * dt / tau;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const double r = rho[q], u = ux[q] * inv_c, v = uy[q] * inv_c;   // u-hat = u / c
+        const double usq15 = 1.5 * (u * u + v * v);
+        S *p = dst + cell_offset(P, q);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            // directional derivative D = d_t + c (e_x d_x + e_y d_y)
+            const double Dr = drho[q] + c * (EX[a] * drho[n + q] + EY[a] * drho[2 * n + q]);
+            const double Du = (dux[q] + c * (EX[a] * dux[n + q] + EY[a] * dux[2 * n + q])) * inv_c;
+            const double Dv = (duy[q] + c * (EX[a] * duy[n + q] + EY[a] * duy[2 * n + q])) * inv_c;
+            const double eu = EX[a] * u + EY[a] * v, eDu = EX[a] * Du + EY[a] * Dv;
+            const double poly = 1.0 + 3.0 * eu + 4.5 * eu * eu - usq15;
+            const double dpoly = 3.0 * eDu + 9.0 * eu * eDu - 3.0 * (u * Du + v * Dv);
+            const double feq = wgt(a) * r * poly;
+            const double f = feq - tau * wgt(a) * (Dr * poly + r * dpoly);
+            const double ft = f + k * (f - feq);
+            p[a * P.plane] = Storage<S>::store((T)(ft - wgt(a) * rho0), a);
         }
     }
 }

@@ -10,9 +10,12 @@
 // stored values once and writes 9 values once; every face value is computed
 // once per wave (the x-face west of each lane, the y-face north of each row).
 //
-// State layout: SoA [9][ny][pitch] of the stored type S.  The stored value of
-// direction a is x_a = f~_a - w_a rho0 (rho0 = 0 gives plain f~), optionally
-// divided by w_a for 16-bit storage.  All stages are affine with coefficients
+// State layout: SoA [9][ny][pitch] of the stored type S, strip-padded: column c of a
+// row lives in slot (c / 62) * 64 + c % 62, so each 62-column strip owns an aligned
+// block of 64 slots (two pad slots) and every wave stores whole cache lines (partial
+// line stores from two waves into one line cost far more HBM time than the 3 % of
+// padding).  The stored value of direction a is x_a = f~_a - w_a rho0 (rho0 = 0 gives
+// plain f~), optionally divided by w_a for 16-bit storage.  All stages are affine with coefficients
 // that sum to one, so the w_a rho0 offset cancels and every formula below runs
 // unchanged on deviations.
 #pragma once
@@ -55,6 +58,11 @@ struct StepParams {
 };
 
 // ---------------------------------------------------------------- storage
+constexpr int STRIP = 62;   // output columns per wave
+constexpr int SLOTS = 64;   // storage slots per strip
+__host__ __device__ __forceinline__ int64_t col_slot(int c) { return (int64_t)(c / STRIP) * SLOTS + c % STRIP; }
+__host__ __device__ __forceinline__ int64_t padded_pitch(int nx) { return (int64_t)((nx + STRIP - 1) / STRIP) * SLOTS; }
+
 template <typename S> struct Storage;
 // (direction indices are compile-time constants once the 9-loops are unrolled)
 template <> struct Storage<double> {
@@ -74,6 +82,16 @@ template <> struct Storage<_Float16> {
     __device__ __forceinline__ static float load(_Float16 v, int a) { return (float)v * (float)wgt(a); }
     __device__ __forceinline__ static _Float16 store(float v, int a) { return (_Float16)(v * (float)inv_wgt(a)); }
 };
+
+// ---------------------------------------------------------------- uniform reads
+// Row metrics are the same for the whole wave.  Reading them through the constant
+// address space makes them scalar loads (counted by lgkmcnt): as vector loads they would
+// share the in-order vmcnt with the next row's prefetch, and waiting for a metric would
+// also wait for the prefetch.
+template <typename T>
+__device__ __forceinline__ T ldc(const T *p, int64_t i) {
+    return ((const __attribute__((address_space(4))) T *)p)[i];
+}
 
 // ---------------------------------------------------------------- wave shifts
 // Wave-wide DPP row moves (GFX9 wave_shr:1 / wave_shl:1).  Out-of-range lanes read 0
@@ -213,6 +231,7 @@ struct March {
     S *__restrict__ dst;
     int lane, col;
     int ccol;                  // column this lane loads (wrapped / clamped)
+    int64_t lslot, sslot;      // storage slot this lane loads / stores
     bool per_x, per_y;
     bool ghostW, ghostE;       // this wave holds the west / east ghost column
     int laneE;                 // lane of column nx
@@ -232,6 +251,10 @@ struct March {
         else ccol = col < 0 ? 0 : (col >= nx ? nx - 1 : col);
         if (ccol >= nx) ccol = nx - 1;   // garbage lanes past a short periodic row
         if (ccol < 0) ccol = 0;
+        lslot = col_slot(ccol);
+        // lanes 1..62 own slots 0..61 of this strip's block, lanes 0 and 63 the two pad
+        // slots: the wave writes its 64-slot block whole (pad values are never read)
+        sslot = (int64_t)(x0 / STRIP) * SLOTS + (lane == 0 ? STRIP : (lane == 63 ? STRIP + 1 : lane - 1));
         ghostW = BND && !per_x && x0 == 0;
         laneE = nx - x0 + 1;
         ghostE = BND && !per_x && laneE <= 63;
@@ -262,7 +285,7 @@ struct March {
         return r < 0 ? r + ny : (r >= ny ? r - ny : r);
     }
     __device__ __forceinline__ void load(int r, S (&raw)[9]) const {
-        const S *p = src + (int64_t)row_index(r) * P.pitch + ccol;
+        const S *p = src + (int64_t)row_index(r) * P.pitch + lslot;
 #pragma unroll
         for (int a = 0; a < 9; ++a) raw[a] = p[a * P.plane];
     }
@@ -361,8 +384,8 @@ struct March {
     // with tangential gradient from neighbouring lanes, Sec. 2.2 / 2.3 (readings R2 / R3).
     __device__ __forceinline__ void yface(int g, const T (&lo)[9], const T (&hi)[9], T (&fb)[9]) const {
         const int ny = P.ny;
-        const T lam = P.ym[g];
-        const T bn = P.hc * P.ym[ny + 1 + g];
+        const T lam = ldc(P.ym, g);
+        const T bn = P.hc * ldc(P.ym, ny + 1 + g);
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
             const T dn = hi[a] - lo[a];
@@ -389,20 +412,25 @@ struct March {
     }
 
     // ---- one output row k.  Pm, P0, Pp = phi rows k-1, k, k+1; S0 = psi row k;
-    // fS = y-face values south of row k.  Produces the row-k update and the
-    // y-face values north of row k (left in fS).  If a next row is needed its
-    // phi / psi go to Pm / Sm.
+    // fS = y-face values south of row k; Rnext = stored values of row k+2 (loaded by the
+    // previous row).  Produces the row-k update and the y-face values north of row k
+    // (left in fS), loads row k+3 into Rnew (two rows of prefetch), and turns Rnext into
+    // phi / psi of row k+2 in Pm / Sm when a next row is needed.
     __device__ __forceinline__ void body(int k, int j1, T (&Pm)[9], T (&P0)[9], T (&Pp)[9], T (&Sm)[9],
-                                         T (&S0)[9], T (&fS)[9]) {
+                                         T (&S0)[9], T (&fS)[9], S (&Rnew)[9], S (&Rnext)[9]) {
         const int ny = P.ny;
         const bool need_next = k + 1 < j1;
         const bool next_real = !BND || (k + 2 < ny) || per_y;
-        S raw[9];
-        if (need_next && next_real) load(k + 2, raw);
+        // The prefetch is issued on every path (a row already loaded when no new row is
+        // needed): with a conditional load the paths would carry different numbers of
+        // memory operations, and the wait for the prefetched row would then also wait for
+        // the previous row's stores.
+        const bool load_real = k + 2 < j1 && (!BND || (k + 3 < ny) || per_y);
+        load(load_real ? k + 3 : k, Rnew);
 
         // x-faces at row k
         T sy[9];
-        const T isy = P.ym[2 * (ny + 1) + k];
+        const T isy = ldc(P.ym, 2 * (ny + 1) + k);
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
             if (EY[a] != 0) sy[a] = (Pp[a] - Pm[a]) * isy;
@@ -423,9 +451,8 @@ struct March {
         face_mix<1>(fN);
 
         // flux divergence and update, Eq. eq_update with the sign of Eq. bkg_fv (reading R1)
-        const T cdy = P.ym[3 * ny + 2 + k];
-        const bool st = lane >= 1 && lane <= 62 && col < P.nx;
-        S *out = dst + (int64_t)k * P.pitch + col;
+        const T cdy = ldc(P.ym, 3 * ny + 2 + k);
+        S *out = dst + (int64_t)k * P.pitch + sslot;
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
             T v = (SCHEME == SCHEME_DUGKS) ? S0[a] : P0[a];
@@ -434,7 +461,7 @@ struct March {
                 v = fma(EX[a] > 0 ? -cdx : cdx, fE - fW[a], v);
             }
             if (EY[a] != 0) v = fma(EY[a] > 0 ? -cdy : cdy, fN[a] - fS[a], v);
-            if (st) out[a * P.plane] = Storage<S>::store(v, a);
+            out[a * P.plane] = Storage<S>::store(v, a);
         }
 #pragma unroll
         for (int a = 0; a < 9; ++a) fS[a] = fN[a];
@@ -442,7 +469,7 @@ struct March {
         // next row (k + 2) into the free slot
         if (need_next) {
             if (next_real) {
-                cell(raw, Pm, Sm);
+                cell(Rnext, Pm, Sm);
                 ghost_x(Pm);
             } else {
                 ghost_y(SIDE_N, Pp, P0, Pm);
@@ -453,26 +480,28 @@ struct March {
     __device__ __forceinline__ void run(int j0, int j1) {
         const int ny = P.ny;
         T PA[9], PB[9], PC[9], SA[9], SB[9], SC[9], fS[9];
-        S raw[9];
-        // prologue: PA = phi[j0-1], PB = phi[j0], PC = phi[j0+1], SB / SC = psi
-        if (BND && j0 == 0 && !per_y) {
-            load(0, raw);
-            cell(raw, PB, SB);
+        S R0[9], R1[9], R2[9], R3[9];
+        // prologue: PA = phi[j0-1], PB = phi[j0], PC = phi[j0+1], SB / SC = psi; all of its
+        // loads, and the first prefetch (row j0 + 2, into R0), are issued before any use
+        const bool south_ghost = BND && j0 == 0 && !per_y;
+        const bool north_ghost = BND && !(j0 + 1 < ny || per_y);   // row j0 + 1 is a ghost row
+        load(south_ghost ? 0 : j0 - 1, R3);
+        load(south_ghost ? 1 : j0, R1);
+        load(south_ghost || north_ghost ? j0 : j0 + 1, R2);
+        load((j0 + 1 < j1 && (!BND || j0 + 2 < ny || per_y)) ? j0 + 2 : j0, R0);
+        if (south_ghost) {
+            cell(R3, PB, SB);   // rows 0 and 1
             ghost_x(PB);
-            load(1, raw);
-            cell(raw, PC, SC);
+            cell(R1, PC, SC);
             ghost_x(PC);
             ghost_y(SIDE_S, PB, PC, PA);
         } else {
-            load(j0 - 1, raw);
-            cell(raw, PA, SA);
+            cell(R3, PA, SA);
             ghost_x(PA);
-            load(j0, raw);
-            cell(raw, PB, SB);
+            cell(R1, PB, SB);
             ghost_x(PB);
-            if (!BND || j0 + 1 < ny || per_y) {
-                load(j0 + 1, raw);
-                cell(raw, PC, SC);
+            if (!north_ghost) {
+                cell(R2, PC, SC);
                 ghost_x(PC);
             } else {
                 ghost_y(SIDE_N, PB, PA, PC);
@@ -483,11 +512,11 @@ struct March {
         face_mix<1>(fS);
 
         for (int k = j0; k < j1; k += 3) {
-            body(k, j1, PA, PB, PC, SA, SB, fS);
+            body(k, j1, PA, PB, PC, SA, SB, fS, R1, R0);
             if (k + 1 >= j1) break;
-            body(k + 1, j1, PB, PC, PA, SB, SC, fS);
+            body(k + 1, j1, PB, PC, PA, SB, SC, fS, R2, R1);
             if (k + 2 >= j1) break;
-            body(k + 2, j1, PC, PA, PB, SC, SA, fS);
+            body(k + 2, j1, PC, PA, PB, SC, SA, fS, R0, R2);
         }
     }
 };

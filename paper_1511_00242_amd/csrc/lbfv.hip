@@ -421,7 +421,7 @@ void init_host_case(HostCase &h, const lbfv_mesh *mesh, const lbfv_velset *vel, 
     else h.variant = V_F32;
     h.rho0 = storage == LBFV_STORE_NATIVE ? 0.0 : rho0;
     h.esize = h.variant == V_F64 ? 8 : (h.variant == V_F32 ? 4 : 2);
-    h.pitch = ((int64_t)h.nx + 63) / 64 * 64;
+    h.pitch = padded_pitch(h.nx);   // strip-padded rows (see kernels.hpp)
     h.plane = h.pitch * h.ny;
 }
 
@@ -638,6 +638,20 @@ int do_steps(lbfv_ctx *c, int scheme, int32_t n) {
 }
 
 template <typename T, typename S>
+int ce_kernel_t(lbfv_ctx *c, const double *d) {
+    HostCase &h = c->hc;
+    double ext[4];
+    current_ext(h, ext);
+    StepParams<T> P = make_params<T>(h, ext);
+    const int64_t n = (int64_t)h.nx * h.ny;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL((init_ce_kernel<T, S>), dim3(blocks), dim3(256), 0, c->stream, P, h.cur, d, d + n, d + 2 * n,
+                       d + 3 * n, d + 6 * n, d + 9 * n, h.c, h.tau, h.dt, h.rho0);
+    HIPCHK(hipGetLastError());
+    return LBFV_OK;
+}
+
+template <typename T, typename S>
 int state_kernel_t(lbfv_ctx *c, int which, const double *d0, const double *d1, const double *d2, double *dout) {
     HostCase &h = c->hc;
     double ext[4];
@@ -800,6 +814,42 @@ int lbfv_init_equilibrium(lbfv_ctx *c, const double *rho, const double *ux, cons
     (void)hipFree(d);
     if (st) return st;
     if (e != hipSuccess) return c->fail(LBFV_EHIP, std::string("init_equilibrium: ") + hipGetErrorString(e));
+    c->has_state = true;
+    c->unstable = false;
+    c->uprev_valid = false;
+    return LBFV_OK;
+}
+
+int lbfv_init_chapman_enskog(lbfv_ctx *c, const double *rho, const double *ux, const double *uy,
+                             const double *drho, const double *dux, const double *duy) {
+    if (!c) return LBFV_EINVAL;
+    if (!rho || !ux || !uy || !drho || !dux || !duy)
+        return c->fail(LBFV_EINVAL, "lbfv_init_chapman_enskog: NULL field");
+    int st = ensure_buffers(c);
+    if (st) return st;
+    HostCase &h = c->hc;
+    const int64_t n = (int64_t)h.nx * h.ny;
+    double *d;
+    st = staging(c, 12 * n, &d);
+    if (st) return st;
+    const double *src[6] = {rho, ux, uy, drho, dux, duy};
+    const int64_t off[6] = {0, n, 2 * n, 3 * n, 6 * n, 9 * n};
+    const int64_t cnt[6] = {n, n, n, 3 * n, 3 * n, 3 * n};
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 6 && e == hipSuccess; ++i)
+        e = hipMemcpyAsync(d + off[i], src[i], cnt[i] * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) {
+        switch (h.variant) {
+        case V_F64: st = ce_kernel_t<double, double>(c, d); break;
+        case V_F32: st = ce_kernel_t<float, float>(c, d); break;
+        case V_BF16: st = ce_kernel_t<float, __bf16>(c, d); break;
+        default: st = ce_kernel_t<float, _Float16>(c, d); break;
+        }
+        e = hipStreamSynchronize(c->stream);
+    }
+    (void)hipFree(d);
+    if (st) return st;
+    if (e != hipSuccess) return c->fail(LBFV_EHIP, std::string("init_chapman_enskog: ") + hipGetErrorString(e));
     c->has_state = true;
     c->unstable = false;
     c->uprev_valid = false;

@@ -29,7 +29,8 @@ LBFV_STORE_NATIVE, LBFV_STORE_DEV_FP32, LBFV_STORE_DEV_BF16, LBFV_STORE_DEV_FP16
 # every function the header declares
 EXPORTS = (
     "lbfv_create", "lbfv_destroy", "lbfv_dt_from_cfl", "lbfv_set_periodic", "lbfv_set_wall",
-    "lbfv_set_inflow_eq", "lbfv_set_outflow_extrap", "lbfv_init_equilibrium", "lbfv_set_f",
+    "lbfv_set_inflow_eq", "lbfv_set_outflow_extrap", "lbfv_init_equilibrium",
+    "lbfv_init_chapman_enskog", "lbfv_set_f",
     "lbfv_get_f", "lbfv_bind_buffers", "lbfv_required_bytes", "dugks_step", "bkg_step",
     "lbfv_moments", "lbfv_totals", "lbfv_residual", "lbfv_set_tile", "lbfv_get_tile",
     "lbfv_autotune", "lbfv_strerror", "lbfv_last_error", "lbfv_batch_create",
@@ -88,6 +89,7 @@ def lib():
             "lbfv_set_inflow_eq": ([vp, ip, C.c_double, C.c_double, C.c_double], ip),
             "lbfv_set_outflow_extrap": ([vp, ip, ip], ip),
             "lbfv_init_equilibrium": ([vp, dp, dp, dp], ip),
+            "lbfv_init_chapman_enskog": ([vp, dp, dp, dp, dp, dp, dp], ip),
             "lbfv_set_f": ([vp, dp], ip),
             "lbfv_get_f": ([vp, dp], ip),
             "lbfv_bind_buffers": ([vp, vp, vp, C.c_size_t], ip),
@@ -220,6 +222,11 @@ class Context:
     def init_equilibrium(self, rho, ux, uy):
         r, u, v = (np.ascontiguousarray(a, dtype=np.float64) for a in (rho, ux, uy))
         _check(lib().lbfv_init_equilibrium(self.h, _p(r), _p(u), _p(v)), self.h)
+
+    def init_chapman_enskog(self, rho, ux, uy, drho, dux, duy):
+        """``drho``, ``dux``, ``duy``: ``[3, ny, nx]`` derivatives along (t, x, y)."""
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (rho, ux, uy, drho, dux, duy)]
+        _check(lib().lbfv_init_chapman_enskog(self.h, *[_p(a) for a in arrs]), self.h)
 
     def set_f(self, f):
         f = np.ascontiguousarray(f, dtype=np.float64)

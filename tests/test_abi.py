@@ -97,7 +97,7 @@ def test_required_bytes_layout():
     xf, yf = I.uniform_faces(100), I.uniform_faces(7)
     for compute, storage, esize in ((0, 0, 8), (1, 0, 4), (1, 1, 4), (1, 2, 2), (1, 3, 2)):
         ctx = L.Context(xf, yf, 0.1, 0.01, compute=compute, storage=storage)
-        assert ctx.required_bytes() == 9 * 7 * 128 * esize   # rows padded to 64 elements
+        assert ctx.required_bytes() == 9 * 7 * 128 * esize   # two 62-column strips, 64 slots each
         ctx.close()
 
 
