@@ -26,6 +26,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+HEADLINE_TILE = (68, 4)        # rows per block, waves per block of the timed 4096^2 step (fixed so that the
+                               # committed counter profile describes the same launches)
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_step_kernel_dugks_fp64_taylor_green_4096.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1511_00242_amd", "csrc", "kernels.hpp")
 BYTES = {"f64": 144, "f32": 72, "bf16": 36, "f16": 36}   # algorithmic bytes per cell-step (9 reads + 9 writes)
 
 
@@ -43,6 +47,18 @@ def parse():
     p.add_argument("--tile", default="", help="rows,waves_per_block for every run (skips the autotuner)")
     p.add_argument("--copy-probe-mb", type=int, default=0,
                    help="also run a plain device copy of this many MiB (calibrates HBM byte counters)")
+    p.add_argument("--cavity-residual", action="store_true",
+                   help="instead of the throughput benchmark: run the 256^2 tanh cavity (Re 1000) toward "
+                        "a steady state and report the residual history")
+    p.add_argument("--scheme", default="dugks", choices=["dugks", "bkg"])
+    p.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    p.add_argument("--target", type=float, default=1e-8, help="residual target (per 1000 steps)")
+    p.add_argument("--budget-s", type=float, default=600.0, help="wall-time budget of the residual run")
+    p.add_argument("--beta", type=float, default=0.0,
+                   help="tanh parameter of the cavity mesh (0: largest adjacent ratio 1.05)")
+    p.add_argument("--save", default="", help="save the final f~ (npy) of the residual run")
+    p.add_argument("--resume", default="", help="start the residual run from a saved f~ (npy)")
+    p.add_argument("--start-step", type=int, default=0, help="step count of the resumed state")
     return p.parse_args()
 
 
@@ -119,6 +135,88 @@ def run_batch(steps, warmup, stream):
                 seq_fp64_ms_per_step=t_seq, speedup_vs_seq_fp64=t_seq / ms)
 
 
+def cavity_residual(a, stream):
+    """Config 1: lid-driven cavity 256^2 on the tanh mesh, U_lid 0.1, Re 1000, from rest,
+    advanced in chunks of 1000 steps until ||u - u_prev|| / ||u|| over a chunk falls below
+    the target or the wall-time budget is spent."""
+    import torch
+    from paper_1511_00242_amd import inputs as I
+    from paper_1511_00242_amd import lbfv as L
+    w = I.cavity(256)
+    if a.beta > 0:
+        w.xf = I.tanh_faces(256, a.beta)
+        w.yf = w.xf.copy()
+        w.dt = I.cfl_dt(w.xf, w.yf, 0.5)
+    scheme = L.LBFV_DUGKS if a.scheme == "dugks" else L.LBFV_BKG
+    comp, sto = (L.LBFV_FP64, L.LBFV_STORE_NATIVE) if a.precision == "fp64" else (L.LBFV_FP32, L.LBFV_STORE_DEV_FP32)
+    ctx = L.Context(w.xf, w.yf, w.tau, w.dt, bcs=w.bcs, compute=comp, storage=sto, check_every=1000,
+                    stream=stream.cuda_stream)
+    if a.resume:
+        ctx.set_f(np.load(a.resume))
+    else:
+        ctx.init_equilibrium(w.rho, w.ux, w.uy)
+    ctx.autotune(scheme, 200)
+    m0 = ctx.totals()[0]
+    ctx.residual()
+    steps, hist, res = a.start_step, [], 1.0
+    t0 = time.perf_counter()
+    gpu_ms = 0.0
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    while time.perf_counter() - t0 < a.budget_s:
+        e0.record(stream)
+        ctx.step(scheme, 1000 * 50)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        gpu_ms += e0.elapsed_time(e1)
+        # the residual is defined over one 1000-step chunk: take it from the last chunk
+        ctx.residual()
+        ctx.step(scheme, 1000)
+        res = ctx.residual()
+        steps += 51000
+        hist.append((steps, res))
+        print(f"[cavity] step {steps} residual {res:.3e} ({time.perf_counter() - t0:.0f} s)",
+              file=sys.stderr, flush=True)
+        if res < a.target:
+            break
+    m1 = ctx.totals()[0]
+    if a.save:
+        np.save(a.save, ctx.get_f())
+    rows, wpb = ctx.get_tile()
+    ctx.close()
+    cells = 256 * 256
+    return {"workload": "cavity_256x256_tanh_re1000", "scheme": a.scheme, "precision": a.precision,
+            "mesh_beta": a.beta or I.tanh_beta_for_ratio(256, 1.05), "dt": w.dt, "tau": w.tau,
+            "steps": steps, "lid_transits": steps * w.dt * 0.1, "residual": res, "target": a.target,
+            "reached": res < a.target, "gpu_s": gpu_ms / 1e3,
+            "mlups": cells * 50000 * len(hist) / (gpu_ms * 1e-3) / 1e6 if gpu_ms else None,
+            "mass_rel_drift": abs(m1 - m0) / m0, "tile": [rows, wpb],
+            "history": [[s_, r_] for s_, r_ in hist[:: max(1, len(hist) // 40)]] + [[steps, res]]}
+
+
+def profiled_traffic(tile, ms_per_step):
+    """HBM traffic of the headline kernel from the committed rocprofv3 counter summary:
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the same counters read for a
+    plain 1 GiB device copy.  None when the kernel source or the launch shape changed since."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None, None
+    kv = {}
+    for line in open(TRAFFIC_PROFILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        if kv.get("kernel_source_sha256") != sha or kv.get("tile") != f"{tile[0]},{tile[1]}":
+            return None, None
+        b = (float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
+             + float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"])) * 1024.0
+    except (KeyError, ValueError):
+        return None, None
+    return b / (ms_per_step * 1e-3) / 1e9, b
+
+
 def cpu_baseline(n, steps):
     """The FP64 oracle on the host's cores over a bounded sample of the workload."""
     from oracle import oracle as O
@@ -146,6 +244,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if a.cavity_residual:
+        print(json.dumps(cavity_residual(a, stream)), flush=True)
+        return
     steps = max(2, a.steps)
     tile = tuple(int(x) for x in a.tile.split(",")) if a.tile else None
     if a.copy_probe_mb:
@@ -160,11 +261,12 @@ def main():
 
     w = I.taylor_green(a.n)
     head = run_single("dugks_fp64", w, L.LBFV_DUGKS, L.LBFV_FP64, L.LBFV_STORE_NATIVE, steps, a.warmup,
-                      a.check_every, stream, tile)
+                      a.check_every, stream, tile or HEADLINE_TILE)
     print(f"[bench] dugks fp64 {a.n}^2: {head['ms_per_step']:.4f} ms/step {head['mlups']:.0f} MLUPS",
           file=sys.stderr, flush=True)
     cells = w.nx * w.ny
     gbs = cells * BYTES["f64"] / (head["ms_per_step"] * 1e-3) / 1e9
+    traffic_gbs, traffic_bytes = profiled_traffic(head["tile"], head["ms_per_step"])
 
     variants = {}
     if not a.no_variants:
@@ -183,6 +285,19 @@ def main():
             r["speedup_vs_dugks_fp64"] = head["ms_per_step"] / r["ms_per_step"]
             variants[name] = r
             print(f"[bench] {name}: {r['ms_per_step']:.4f} ms/step {r['mlups']:.0f} MLUPS", file=sys.stderr,
+                  flush=True)
+        # the smaller workloads (L2 / Infinity-Cache resident, launch bound): MLUPS only
+        small = [("tg32_dugks_fp64", I.taylor_green(32), L.LBFV_DUGKS),
+                 ("cavity256_dugks_fp64", I.cavity(256), L.LBFV_DUGKS),
+                 ("cavity256_bkg_fp64", I.cavity(256), L.LBFV_BKG),
+                 ("bl512x256_dugks_fp64", I.boundary_layer(), L.LBFV_DUGKS)]
+        for name, ws, sch in small:
+            if only and name not in only:
+                continue
+            r = run_single(name, ws, sch, L.LBFV_FP64, L.LBFV_STORE_NATIVE, 10 * steps, a.warmup,
+                           a.check_every * 10, stream, tile)
+            variants[name] = r
+            print(f"[bench] {name}: {r['ms_per_step'] * 1e3:.2f} us/step {r['mlups']:.0f} MLUPS", file=sys.stderr,
                   flush=True)
         if not only or "batch" in only:
             r = run_batch(100, 100, stream)
@@ -210,7 +325,8 @@ def main():
                    "check_every": a.check_every, "tile_rows_waves": head["tile"],
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": traffic_gbs,
+                     "traffic_bytes_per_launch": traffic_bytes,
                      "kernel": "lbfv::step_kernel<double,double,DUGKS>",
                      "bytes_per_cell_step": BYTES["f64"]},
         "variants": variants,

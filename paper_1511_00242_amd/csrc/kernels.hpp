@@ -461,7 +461,8 @@ struct March {
                 v = fma(EX[a] > 0 ? -cdx : cdx, fE - fW[a], v);
             }
             if (EY[a] != 0) v = fma(EY[a] > 0 ? -cdy : cdy, fN[a] - fS[a], v);
-            out[a * P.plane] = Storage<S>::store(v, a);
+            // streaming store: the new state is not read again within this step
+            __builtin_nontemporal_store(Storage<S>::store(v, a), out + a * P.plane);
         }
 #pragma unroll
         for (int a = 0; a < 9; ++a) fS[a] = fN[a];
