@@ -42,7 +42,7 @@ def parse():
     p.add_argument("--check-every", type=int, default=100)
     p.add_argument("--no-variants", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
-    p.add_argument("--cpu-steps", type=int, default=3)
+    p.add_argument("--cpu-steps", type=int, default=12)
     p.add_argument("--only", default="", help="comma list of variant names to run")
     p.add_argument("--tile", default="", help="rows,waves_per_block for every run (skips the autotuner)")
     p.add_argument("--copy-probe-mb", type=int, default=0,
@@ -50,6 +50,10 @@ def parse():
     p.add_argument("--cavity-residual", action="store_true",
                    help="instead of the throughput benchmark: run the 256^2 tanh cavity (Re 1000) toward "
                         "a steady state and report the residual history")
+    p.add_argument("--stability-map", action="store_true",
+                   help="instead of the throughput benchmark: the stable band of dt/tau against CFL for "
+                        "the uniform 32^2 and 64^2 cavity, both schemes, one batch per scheme")
+    p.add_argument("--map-steps", type=int, default=20000, help="steps after which a case counts as stable")
     p.add_argument("--scheme", default="dugks", choices=["dugks", "bkg"])
     p.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     p.add_argument("--target", type=float, default=1e-8, help="residual target (per 1000 steps)")
@@ -117,22 +121,28 @@ def run_batch(steps, warmup, stream):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     b.close()
-    # the same cases stepped one at a time with the plain FP64 kernel
-    t_seq = 0.0
-    for w in cases:
-        ctx = L.Context(w.xf, w.yf, w.tau, w.dt, bcs=w.bcs, check_every=0, stream=stream.cuda_stream)
-        ctx.init_equilibrium(w.rho, w.ux, w.uy)
-        ctx.dugks_step(4)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        ctx.dugks_step(32)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        t_seq += e0.elapsed_time(e1) / 32
-        ctx.close()
+    # the same cases stepped one at a time: the plain FP64 kernel, and the FP32 deviation kernel
+    t_seq = {}
+    for label, compute, storage in (("fp64", L.LBFV_FP64, L.LBFV_STORE_NATIVE),
+                                    ("fp32dev", L.LBFV_FP32, L.LBFV_STORE_DEV_FP32)):
+        t_seq[label] = 0.0
+        for w in cases:
+            ctx = L.Context(w.xf, w.yf, w.tau, w.dt, bcs=w.bcs, compute=compute, storage=storage,
+                            check_every=0, stream=stream.cuda_stream)
+            ctx.init_equilibrium(w.rho, w.ux, w.uy)
+            ctx.dugks_step(4)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            ctx.dugks_step(32)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t_seq[label] += e0.elapsed_time(e1) / 32
+            ctx.close()
     return dict(name="batch96_dugks_fp32dev", cases=len(cases), cells=cells, work_items=items,
                 ms_per_step=ms, mlups=cells / (ms * 1e-3) / 1e6, gbs=cells * BYTES["f32"] / (ms * 1e-3) / 1e9,
-                seq_fp64_ms_per_step=t_seq, speedup_vs_seq_fp64=t_seq / ms)
+                hbm_frac=cells * BYTES["f32"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                seq_fp64_ms_per_step=t_seq["fp64"], speedup_vs_seq_fp64=t_seq["fp64"] / ms,
+                seq_fp32dev_ms_per_step=t_seq["fp32dev"], speedup_vs_seq_fp32dev=t_seq["fp32dev"] / ms)
 
 
 def cavity_residual(a, stream):
@@ -194,6 +204,65 @@ def cavity_residual(a, stream):
             "history": [[s_, r_] for s_, r_ in hist[:: max(1, len(hist) // 40)]] + [[steps, res]]}
 
 
+def stability_map(a, stream):
+    """Stable range of the lid-driven cavity (Sec. 3.2, uniform N x N meshes, U_w = 0.1, L = 1)
+    over CFL and dt/tau: every (N, CFL, dt/tau) point is one case of an FP64 batch, advanced
+    from rest for `map_steps` steps; a case is unstable if any cell then holds a non-finite
+    value.  For each (scheme, N, CFL) the band of dt/tau over which the grid points are
+    stable is reported (the longest run of stable points), with the whole row of flags."""
+    import torch
+    from paper_1511_00242_amd import inputs as I
+    from paper_1511_00242_amd import lbfv as L
+    sizes = (32, 64)
+    cfls = [round(0.1 * k, 1) for k in range(1, 13)]
+    ratios = [float(r) for r in np.geomspace(0.1, 1000.0, 41)]
+    grid = [(n, c, r) for n in sizes for c in cfls for r in ratios]
+    out = {"workload": "cavity_uniform_stability_map", "sizes": list(sizes), "cfl": cfls,
+           "dt_over_tau": ratios, "steps": a.map_steps, "precision": "fp64", "schemes": {}}
+    t0 = time.perf_counter()
+    for sname, scheme in (("dugks", L.LBFV_DUGKS), ("bkg", L.LBFV_BKG)):
+        cases = []
+        for n, cfl, r in grid:
+            xf = I.uniform_faces(n)
+            dt = I.cfl_dt(xf, xf, cfl)
+            z = np.zeros((n, n))
+            cases.append(I.Workload(f"cavity_{n}_cfl{cfl}_r{r:.3g}", xf, xf.copy(), dt / r, dt,
+                                    [("wall", 0.0, 0.0), ("wall", 0.0, 0.0), ("wall", 0.0, 0.0),
+                                     ("wall", 0.1, 0.0)], z + 1.0, z, z.copy()))
+        b = L.Batch(cases, compute=L.LBFV_FP64, storage=L.LBFV_STORE_NATIVE, stream=stream.cuda_stream)
+        for i, w in enumerate(cases):
+            b.init_equilibrium(i, w.rho, w.ux, w.uy)
+        done = 0
+        while done < a.map_steps:
+            k = min(5000, a.map_steps - done)
+            b.step(scheme, k)
+            torch.cuda.synchronize()
+            done += k
+            print(f"[stability] {sname}: {done}/{a.map_steps} steps ({time.perf_counter() - t0:.0f} s)",
+                  file=sys.stderr, flush=True)
+        bad = b.nonfinite()
+        b.close()
+        table = {}
+        for n in sizes:
+            for cfl in cfls:
+                flags = [bool(bad[grid.index((n, cfl, r))] == 0) for r in ratios]
+                # the longest run of stable grid points: the stable band of dt/tau
+                best, start = (0, 0), None
+                for k, ok in enumerate(flags + [False]):
+                    if ok and start is None:
+                        start = k
+                    if not ok and start is not None:
+                        if k - start > best[1] - best[0]:
+                            best = (start, k)
+                        start = None
+                band = [ratios[best[0]], ratios[best[1] - 1]] if best[1] > best[0] else None
+                table[f"N{n}_cfl{cfl}"] = {"stable_dt_over_tau": band,
+                                           "stable": "".join("s" if f else "u" for f in flags)}
+        out["schemes"][sname] = table
+    out["wall_s"] = time.perf_counter() - t0
+    return out
+
+
 def profiled_traffic(tile, ms_per_step):
     """HBM traffic of the headline kernel from the committed rocprofv3 counter summary:
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the same counters read for a
@@ -244,6 +313,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if a.stability_map:
+        print(json.dumps(stability_map(a, stream)), flush=True)
+        return
     if a.cavity_residual:
         print(json.dumps(cavity_residual(a, stream)), flush=True)
         return
@@ -264,9 +336,13 @@ def main():
                       a.check_every, stream, tile or HEADLINE_TILE)
     print(f"[bench] dugks fp64 {a.n}^2: {head['ms_per_step']:.4f} ms/step {head['mlups']:.0f} MLUPS",
           file=sys.stderr, flush=True)
+    # the roofline figure divides by the step kernel's own average duration: the same launches
+    # without the periodic check reductions
+    kern = run_single("dugks_fp64_kernel", w, L.LBFV_DUGKS, L.LBFV_FP64, L.LBFV_STORE_NATIVE, steps,
+                      a.warmup, 0, stream, tuple(head["tile"]))
     cells = w.nx * w.ny
-    gbs = cells * BYTES["f64"] / (head["ms_per_step"] * 1e-3) / 1e9
-    traffic_gbs, traffic_bytes = profiled_traffic(head["tile"], head["ms_per_step"])
+    gbs = cells * BYTES["f64"] / (kern["ms_per_step"] * 1e-3) / 1e9
+    traffic_gbs, traffic_bytes = profiled_traffic(head["tile"], kern["ms_per_step"])
 
     variants = {}
     if not a.no_variants:
@@ -328,6 +404,7 @@ def main():
                      "frac": gbs / HBM_PEAK_GBS, "traffic": traffic_gbs,
                      "traffic_bytes_per_launch": traffic_bytes,
                      "kernel": "lbfv::step_kernel<double,double,DUGKS>",
+                     "kernel_ms": kern["ms_per_step"],
                      "bytes_per_cell_step": BYTES["f64"]},
         "variants": variants,
         "context": {"paper_cpu_mlups_64x64": {"dugks": 2.08, "bkg": 3.90,

@@ -49,7 +49,10 @@ typedef enum {
     LBFV_EUNSUPPORTED = -6   /* valid request that this build does not provide */
 } lbfv_status;
 
-enum { LBFV_DUGKS = 0, LBFV_BKG = 1 };
+/* Interface-value schemes.  DUGKS and BKG are the two methods compared; CENTRAL and UPWIND
+ * are the collision-free interface values of Sec. 2.4 (Eqs. cfd1, cfd2), provided to show
+ * the numerical viscosity that ignoring the collision term introduces. */
+enum { LBFV_DUGKS = 0, LBFV_BKG = 1, LBFV_CENTRAL = 2, LBFV_UPWIND = 3 };
 enum { LBFV_WEST = 0, LBFV_EAST = 1, LBFV_SOUTH = 2, LBFV_NORTH = 3 };
 enum { LBFV_X = 0, LBFV_Y = 1 };
 enum { LBFV_FP64 = 0, LBFV_FP32 = 1 };
@@ -131,6 +134,12 @@ int lbfv_required_bytes(const lbfv_ctx *ctx, size_t *bytes_per_buffer);
  * has been set. */
 int dugks_step(lbfv_ctx *ctx, int32_t nsteps);
 int bkg_step(lbfv_ctx *ctx, int32_t nsteps);
+/* Any of the four schemes.  CENTRAL (Eq. cfd1): the face value is f^n interpolated to the
+ * face centre; UPWIND (Eq. cfd2): f^n traced back by h along xi with the stencil of
+ * Eq. f_left.  Both use f = (2 tau f~ + dt feq)/(2 tau + dt) of the cells and the same
+ * update f~^{n+1} = f~+ - dt/|V| sum (xi.n) f_b S as the other two.  EINVAL for an
+ * unknown scheme; otherwise as dugks_step. */
+int lbfv_step(lbfv_ctx *ctx, int scheme, int32_t nsteps);
 
 /* Observables, FP64, synchronising the stream.
  * lbfv_moments: rho = sum f~, rho u = sum xi f~ (Sec. 2.2, Eq. macro_var).
@@ -181,7 +190,11 @@ int lbfv_batch_get_f(lbfv_batch *b, int32_t case_id, double *f);
  * the graph length K run as graph replays, the rest as single launches. */
 int lbfv_batch_step(lbfv_batch *b, int scheme, int32_t nsteps);
 int lbfv_batch_moments(lbfv_batch *b, int32_t case_id, double *rho, double *ux, double *uy);
-/* Graph length K (default 100) and rows per row block of the work list. */
+/* Per-case count of cells whose stored values or FP64 moments are not finite (count[n],
+ * caller-allocated); synchronises the stream.  This is the per-case form of the
+ * non-finite check, used to map the stable range of (CFL, dt/tau) (Sec. 3.2). */
+int lbfv_batch_nonfinite(lbfv_batch *b, int32_t *count);
+/* Graph length K (default 100) and rows per row block of the work list (default 8). */
 int lbfv_batch_set_shape(lbfv_batch *b, int32_t graph_steps, int32_t rows);
 int lbfv_batch_info(const lbfv_batch *b, int64_t *total_cells, int32_t *work_items);
 int lbfv_batch_destroy(lbfv_batch *b);

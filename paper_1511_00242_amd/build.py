@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc", "lbfv.hip")
 LIB = os.path.join(PKG, "liblbfv.so")
 DEPS = [SRC, os.path.join(PKG, "csrc", "kernels.hpp"), os.path.join(PKG, "csrc", "aux_kernels.hpp"),
-        os.path.join(ROOT, "include", "lbfv.h")]
+        os.path.join(PKG, "csrc", "batch_kernels.hpp"), os.path.join(ROOT, "include", "lbfv.h")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -190,4 +190,29 @@ __global__ __launch_bounds__(RED_BLOCK) void reduce_final_kernel(const double *p
     block_sum(v, sh, out);
 }
 
+// Batched form: number of cells holding a non-finite stored value or moment, one block
+// per case, written to count[case] (no atomics, nothing to clear beforehand).
+template <typename T, typename S>
+__global__ __launch_bounds__(RED_BLOCK) void batch_nonfinite_kernel(const StepParams<T> *__restrict__ cases,
+                                                                    int parity, double rho0, double c,
+                                                                    int32_t *count) {
+    __shared__ int sh[RED_BLOCK];
+    const StepParams<T> &P = cases[blockIdx.x];
+    const int64_t n = (int64_t)P.nx * P.ny;
+    const S *src = (const S *)P.buf[parity];
+    int bad = 0;
+    for (int64_t k = threadIdx.x; k < n; k += RED_BLOCK) {
+        double r, u, w;
+        bad += cell_moments64(P, src, k, rho0, c, r, u, w) ? 0 : 1;
+    }
+    const int t = threadIdx.x;
+    sh[t] = bad;
+    __syncthreads();
+    for (int s = RED_BLOCK / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    if (t == 0) count[blockIdx.x] = sh[0];
+}
+
 }  // namespace lbfv

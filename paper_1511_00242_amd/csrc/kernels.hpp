@@ -26,7 +26,10 @@ namespace lbfv {
 
 enum { BC_PERIODIC = 0, BC_WALL = 1, BC_INFLOW = 2, BC_OUTFLOW = 3 };
 enum { SIDE_W = 0, SIDE_E = 1, SIDE_S = 2, SIDE_N = 3 };
-enum { SCHEME_DUGKS = 0, SCHEME_BKG = 1 };
+// Kernel forms: DUGKS and BKG.  The collision-free face values of Sec. 2.4 (central,
+// Eq. cfd1; upwind, Eq. cfd2) run the DUGKS kernel with phi = f, no face back-transform
+// and, for the central form, no trace (coefficients set on the host).
+enum { SCHEME_DUGKS = 0, SCHEME_BKG = 1, SCHEME_CENTRAL = 2, SCHEME_UPWIND = 3 };
 
 // D2Q9 unit directions e_a (xi_a = c e_a, c = sqrt(3 RT)) and weights, Sec. 2.1.
 constexpr int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -522,19 +525,24 @@ struct March {
     }
 };
 
-// One launch = one time step of one case.  Work item w -> (strip, row block); each wave
-// takes one item.  Blocks are renumbered so that consecutive work lands on the same XCD
-// (the hardware deals blocks to the 8 XCDs round-robin).
-template <typename T, typename S, int SCHEME, bool BND>
-__global__ __launch_bounds__(256) void step_kernel(StepParams<T> P, int parity, int rows, int nstrips,
-                                                   int nwork) {
-    const int nb = gridDim.x;
-    int b = blockIdx.x;
+// Logical block index such that consecutive logical blocks run on one XCD: the
+// hardware hands blocks to the 8 XCDs round robin, and neighbouring strips and row
+// blocks share halo lines that are then served by the same L2.
+__device__ __forceinline__ int xcd_block() {
+    const int nb = gridDim.x, b = blockIdx.x;
+    if (nb < 16) return b;
     const int per = (nb + 7) / 8;
     const int xcd = b % 8, slot = b / 8;
     const int full = nb % 8 == 0 ? 8 : nb % 8;   // XCDs that receive `per` blocks
-    int rb = xcd < full ? xcd * per + slot : full * per + (xcd - full) * (per - 1) + slot;
-    if (nb < 16) rb = b;
+    return xcd < full ? xcd * per + slot : full * per + (xcd - full) * (per - 1) + slot;
+}
+
+// One launch = one time step of one case.  Work item w -> (strip, row block); each wave
+// takes one item, and consecutive items (neighbouring strips, then row blocks) share an XCD.
+template <typename T, typename S, int SCHEME, bool BND>
+__global__ __launch_bounds__(256) void step_kernel(StepParams<T> P, int parity, int rows, int nstrips,
+                                                   int nwork) {
+    const int rb = xcd_block();
     const int wpb = blockDim.x >> 6;
     const int w = __builtin_amdgcn_readfirstlane(rb * wpb + (int)(threadIdx.x >> 6));
     if (w >= nwork) return;
@@ -544,30 +552,6 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams<T> P, int parity, 
     S *dst = (S *)P.buf[parity ^ 1];
     March<T, S, SCHEME, BND> m(P, src, dst, 62 * sx);
     m.run(j0, j1);
-}
-
-// Work item of the batched form: case id, strip x0, rows [j0, j1).
-struct BatchItem {
-    int32_t c, x0, j0, j1;
-};
-
-// Batched persistent form: every wave walks the flat work list over all cases with a
-// grid stride; each case carries its own mesh, tau, dt, boundaries and buffers.
-template <typename T, typename S, int SCHEME, bool BND>
-__global__ __launch_bounds__(256) void batch_kernel(const StepParams<T> *__restrict__ cases,
-                                                    const BatchItem *__restrict__ items, int nitems,
-                                                    int parity) {
-    const int wpb = blockDim.x >> 6;
-    const int nw = gridDim.x * wpb;
-    int w = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (int)(threadIdx.x >> 6));
-    for (; w < nitems; w += nw) {
-        const BatchItem it = items[w];
-        const StepParams<T> P = cases[it.c];
-        const S *src = (const S *)P.buf[parity];
-        S *dst = (S *)P.buf[parity ^ 1];
-        March<T, S, SCHEME, BND> m(P, src, dst, it.x0);
-        m.run(it.j0, it.j1);
-    }
 }
 
 }  // namespace lbfv

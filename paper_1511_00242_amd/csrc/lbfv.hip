@@ -3,6 +3,7 @@
 // The public ABI is include/lbfv.h.
 #include "lbfv.h"
 #include "aux_kernels.hpp"
+#include "batch_kernels.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -64,7 +65,7 @@ struct lbfv_ctx {
     int rows = 0, wpb = 4;
     // graphs of `gsteps` launches, per scheme and starting buffer
     int gsteps = 32;
-    hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    hipGraphExec_t gexec[4][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
     // reductions
     double *d_partial = nullptr, *d_out = nullptr, *h_out = nullptr, *d_uprev = nullptr;
     int red_blocks = 0;
@@ -87,9 +88,10 @@ struct lbfv_batch {
     hipStream_t stream = nullptr;
     void *d_params = nullptr;        // StepParams<T>[n]
     BatchItem *d_items = nullptr;
-    int nitems = 0, rows = 16, gsteps = 100;
+    int nitems = 0, rows = 8, gsteps = 100;      // rows: from a sweep on the 96-case batch
     int parity = 0;                  // all cases share the step parity
     bool bnd = false;                // some case has a non-periodic side
+    int slots[2] = {0, 0};           // resident waves of the batch kernel, per scheme
     hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     bool has_state = false;
     std::string last_error;
@@ -143,7 +145,7 @@ void copy_as(const std::vector<double> &in, std::vector<T> &out) {
 }
 
 template <typename T>
-StepParams<T> make_params(const HostCase &h, double ext[4]) {
+StepParams<T> make_params(const HostCase &h, double ext[4], int scheme = SCHEME_DUGKS) {
     StepParams<T> P;
     memset(&P, 0, sizeof(P));
     P.buf[0] = h.buf[0];
@@ -174,6 +176,14 @@ StepParams<T> make_params(const HostCase &h, double ext[4]) {
     P.cb = (T)(3.0 * hh / (2.0 * tau + dt));
     P.cd = (T)(2.0 * dt / (2.0 * tau + dt));
     P.m2 = (T)(hh / (2.0 * tau + hh));
+    if (scheme == SCHEME_CENTRAL || scheme == SCHEME_UPWIND) {
+        // Sec. 2.4, Eqs. cfd1 / cfd2: the face value is built from f itself,
+        // f = x + dt/(2 tau + dt) (feq - x), and is used as it is (collision ignored);
+        // the central form takes no characteristic trace.
+        P.cb = (T)(dt / (2.0 * tau + dt));
+        P.m2 = (T)0;
+        if (scheme == SCHEME_CENTRAL) P.hc = (T)0;
+    }
     return P;
 }
 
@@ -240,8 +250,8 @@ StepShape step_shape(const HostCase &h, int rows, int wpb) {
 
 template <typename T, typename S, bool BND>
 void *step_fn_b(int scheme) {
-    return scheme == SCHEME_DUGKS ? (void *)step_kernel<T, S, SCHEME_DUGKS, BND>
-                                  : (void *)step_kernel<T, S, SCHEME_BKG, BND>;
+    return scheme == SCHEME_BKG ? (void *)step_kernel<T, S, SCHEME_BKG, BND>
+                                : (void *)step_kernel<T, S, SCHEME_DUGKS, BND>;
 }
 template <typename T, typename S>
 void *step_fn(int scheme, bool bnd) {
@@ -292,10 +302,10 @@ struct StepArgs {
     }
 };
 
-void fill_args(const HostCase &h, const double ext[4], const StepShape &sh, int parity, StepArgs &a) {
+void fill_args(const HostCase &h, const double ext[4], const StepShape &sh, int parity, int scheme, StepArgs &a) {
     double e[4] = {ext[0], ext[1], ext[2], ext[3]};
-    if (is_f64(h.variant)) a.pd = make_params<double>(h, e);
-    else a.pf = make_params<float>(h, e);
+    if (is_f64(h.variant)) a.pd = make_params<double>(h, e, scheme);
+    else a.pf = make_params<float>(h, e, scheme);
     a.parity = parity;
     a.rows = sh.rows;
     a.nstrips = sh.nstrips;
@@ -491,7 +501,7 @@ int launch_one(lbfv_ctx *c, int scheme, int parity, const double ext[4]) {
     HostCase &h = c->hc;
     StepShape sh = step_shape(h, c->rows, c->wpb);
     StepArgs a;
-    fill_args(h, ext, sh, parity, a);
+    fill_args(h, ext, sh, parity, scheme, a);
     HIPCHK(hipLaunchKernel(step_fn_variant(h.variant, scheme, has_boundary(h)), dim3(sh.nblocks), dim3(64 * sh.wpb), a.args, 0,
                            c->stream));
     return LBFV_OK;
@@ -505,7 +515,7 @@ int build_graph(lbfv_ctx *c, int scheme, int parity0, const double ext[4]) {
     hipGraphNode_t prev = nullptr;
     for (int s = 0; s < c->gsteps; ++s) {
         StepArgs a;
-        fill_args(h, ext, sh, (parity0 + s) & 1, a);
+        fill_args(h, ext, sh, (parity0 + s) & 1, scheme, a);
         hipKernelNodeParams kp;
         memset(&kp, 0, sizeof(kp));
         kp.func = step_fn_variant(h.variant, scheme, has_boundary(h));
@@ -901,6 +911,11 @@ int lbfv_get_f(lbfv_ctx *c, double *f) {
 
 int dugks_step(lbfv_ctx *c, int32_t n) { return do_steps(c, SCHEME_DUGKS, n); }
 int bkg_step(lbfv_ctx *c, int32_t n) { return do_steps(c, SCHEME_BKG, n); }
+int lbfv_step(lbfv_ctx *c, int scheme, int32_t n) {
+    if (!c) return LBFV_EINVAL;
+    if (scheme < LBFV_DUGKS || scheme > LBFV_UPWIND) return c->fail(LBFV_EINVAL, "unknown scheme");
+    return do_steps(c, scheme, n);
+}
 
 int lbfv_moments(lbfv_ctx *c, double *rho, double *ux, double *uy) {
     if (!c) return LBFV_EINVAL;
@@ -1010,7 +1025,8 @@ int size_class(int n) {
 
 std::string tune_key(const HostCase &h, int scheme) {
     std::ostringstream s;
-    s << arch_name() << " " << (scheme == SCHEME_DUGKS ? "dugks" : "bkg") << " v" << h.variant << " x"
+    static const char *names[4] = {"dugks", "bkg", "central", "upwind"};
+    s << arch_name() << " " << names[scheme] << " v" << h.variant << " x"
       << size_class(h.nx) << " y" << size_class(h.ny);
     return s.str();
 }
@@ -1047,7 +1063,7 @@ void cache_store(const char *path, const std::string &key, int rows, int wpb, do
 extern "C" int lbfv_autotune(lbfv_ctx *c, int scheme, int32_t trial_steps, const char *cache_path,
                              double *best_ms) {
     if (!c) return LBFV_EINVAL;
-    if (scheme != LBFV_DUGKS && scheme != LBFV_BKG) return c->fail(LBFV_EINVAL, "unknown scheme");
+    if (scheme < LBFV_DUGKS || scheme > LBFV_UPWIND) return c->fail(LBFV_EINVAL, "unknown scheme");
     if (trial_steps < 1) return c->fail(LBFV_EINVAL, "trial_steps must be >= 1");
     if (!c->has_state) return c->fail(LBFV_ESTATE, "autotune needs a state to step");
     if (!c->hc.sides_set()) return c->fail(LBFV_ESTATE, "all four sides must be set");
@@ -1196,15 +1212,21 @@ struct BatchArgs {
     }
 };
 
-int batch_grid(const lbfv_batch *b) {
-    // persistent: at most 8 waves per CU resident on 256 CUs, 4 waves per block
-    return std::max(1, std::min((b->nitems + 3) / 4, 256 * 2));
+// Persistent grid: exactly the blocks of 4 waves that fit on the device at once (from
+// the kernel's occupancy), capped by the work list.
+int batch_grid(lbfv_batch *b, int scheme) {
+    int &slots = b->slots[scheme];
+    if (slots <= 0) {
+        slots = resident_waves(batch_fn_variant(b->variant, scheme, b->bnd), 4);
+        if (slots <= 0) slots = 256 * 8;
+    }
+    return std::max(1, std::min((b->nitems + 3) / 4, slots / 4));
 }
 
 int batch_launch_one(lbfv_batch *b, int scheme, int parity) {
     BatchArgs a{b->d_params, b->d_items, b->nitems, parity};
     a.bind();
-    hipError_t e = hipLaunchKernel(batch_fn_variant(b->variant, scheme, b->bnd), dim3(batch_grid(b)), dim3(256), a.args, 0,
+    hipError_t e = hipLaunchKernel(batch_fn_variant(b->variant, scheme, b->bnd), dim3(batch_grid(b, scheme)), dim3(256), a.args, 0,
                                    b->stream);
     if (e != hipSuccess) return b->fail(LBFV_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
     return LBFV_OK;
@@ -1220,7 +1242,7 @@ int batch_build_graph(lbfv_batch *b, int scheme, int parity0) {
         hipKernelNodeParams kp;
         memset(&kp, 0, sizeof(kp));
         kp.func = batch_fn_variant(b->variant, scheme, b->bnd);
-        kp.gridDim = dim3(batch_grid(b));
+        kp.gridDim = dim3(batch_grid(b, scheme));
         kp.blockDim = dim3(256);
         kp.kernelParams = a.args;
         hipGraphNode_t node;
@@ -1440,6 +1462,42 @@ int lbfv_batch_moments(lbfv_batch *b, int32_t ci, double *rho, double *ux, doubl
     memcpy(rho, tmp.data(), n * 8);
     memcpy(ux, tmp.data() + n, n * 8);
     memcpy(uy, tmp.data() + 2 * n, n * 8);
+    return LBFV_OK;
+}
+
+int lbfv_batch_nonfinite(lbfv_batch *b, int32_t *count) {
+    if (!b) return LBFV_EINVAL;
+    if (!count) return b->fail(LBFV_EINVAL, "NULL count array");
+    const int n = (int)b->cases.size();
+    int32_t *d;
+    if (hipMalloc((void **)&d, n * sizeof(int32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        return b->fail(LBFV_ENOMEM, "staging");
+    }
+    const double c = b->cases[0].c, rho0 = b->cases[0].rho0;
+    switch (b->variant) {
+    case V_F64:
+        hipLaunchKernelGGL((batch_nonfinite_kernel<double, double>), dim3(n), dim3(RED_BLOCK), 0, b->stream,
+                           (const StepParams<double> *)b->d_params, b->parity, rho0, c, d);
+        break;
+    case V_F32:
+        hipLaunchKernelGGL((batch_nonfinite_kernel<float, float>), dim3(n), dim3(RED_BLOCK), 0, b->stream,
+                           (const StepParams<float> *)b->d_params, b->parity, rho0, c, d);
+        break;
+    case V_BF16:
+        hipLaunchKernelGGL((batch_nonfinite_kernel<float, __bf16>), dim3(n), dim3(RED_BLOCK), 0, b->stream,
+                           (const StepParams<float> *)b->d_params, b->parity, rho0, c, d);
+        break;
+    default:
+        hipLaunchKernelGGL((batch_nonfinite_kernel<float, _Float16>), dim3(n), dim3(RED_BLOCK), 0, b->stream,
+                           (const StepParams<float> *)b->d_params, b->parity, rho0, c, d);
+        break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(count, d, n * sizeof(int32_t), hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return b->fail(LBFV_EHIP, std::string("batch check: ") + hipGetErrorString(e));
     return LBFV_OK;
 }
 

@@ -20,7 +20,7 @@ import numpy as np
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblbfv.so")
 
 LBFV_OK, LBFV_EINVAL, LBFV_ESTATE, LBFV_ENOMEM, LBFV_EHIP, LBFV_EUNSTABLE, LBFV_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-LBFV_DUGKS, LBFV_BKG = 0, 1
+LBFV_DUGKS, LBFV_BKG, LBFV_CENTRAL, LBFV_UPWIND = 0, 1, 2, 3
 LBFV_WEST, LBFV_EAST, LBFV_SOUTH, LBFV_NORTH = 0, 1, 2, 3
 LBFV_X, LBFV_Y = 0, 1
 LBFV_FP64, LBFV_FP32 = 0, 1
@@ -31,11 +31,12 @@ EXPORTS = (
     "lbfv_create", "lbfv_destroy", "lbfv_dt_from_cfl", "lbfv_set_periodic", "lbfv_set_wall",
     "lbfv_set_inflow_eq", "lbfv_set_outflow_extrap", "lbfv_init_equilibrium",
     "lbfv_init_chapman_enskog", "lbfv_set_f",
-    "lbfv_get_f", "lbfv_bind_buffers", "lbfv_required_bytes", "dugks_step", "bkg_step",
+    "lbfv_get_f", "lbfv_bind_buffers", "lbfv_required_bytes", "dugks_step", "bkg_step", "lbfv_step",
     "lbfv_moments", "lbfv_totals", "lbfv_residual", "lbfv_set_tile", "lbfv_get_tile",
     "lbfv_autotune", "lbfv_strerror", "lbfv_last_error", "lbfv_batch_create",
     "lbfv_batch_init_equilibrium", "lbfv_batch_set_f", "lbfv_batch_get_f", "lbfv_batch_step",
-    "lbfv_batch_moments", "lbfv_batch_set_shape", "lbfv_batch_info", "lbfv_batch_destroy",
+    "lbfv_batch_moments", "lbfv_batch_nonfinite", "lbfv_batch_set_shape", "lbfv_batch_info",
+    "lbfv_batch_destroy",
 )
 
 
@@ -96,6 +97,7 @@ def lib():
             "lbfv_required_bytes": ([vp, C.POINTER(C.c_size_t)], ip),
             "dugks_step": ([vp, C.c_int32], ip),
             "bkg_step": ([vp, C.c_int32], ip),
+            "lbfv_step": ([vp, ip, C.c_int32], ip),
             "lbfv_moments": ([vp, dp, dp, dp], ip),
             "lbfv_totals": ([vp, dp], ip),
             "lbfv_residual": ([vp, dp], ip),
@@ -111,6 +113,7 @@ def lib():
             "lbfv_batch_get_f": ([vp, C.c_int32, dp], ip),
             "lbfv_batch_step": ([vp, ip, C.c_int32], ip),
             "lbfv_batch_moments": ([vp, C.c_int32, dp, dp, dp], ip),
+            "lbfv_batch_nonfinite": ([vp, C.POINTER(C.c_int32)], ip),
             "lbfv_batch_set_shape": ([vp, C.c_int32, C.c_int32], ip),
             "lbfv_batch_info": ([vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)], ip),
             "lbfv_batch_destroy": ([vp], ip),
@@ -264,7 +267,12 @@ class Context:
         _check(lib().bkg_step(self.h, int(n)), self.h)
 
     def step(self, scheme: int, n: int = 1):
-        (self.dugks_step if scheme == LBFV_DUGKS else self.bkg_step)(n)
+        if scheme == LBFV_DUGKS:
+            self.dugks_step(n)
+        elif scheme == LBFV_BKG:
+            self.bkg_step(n)
+        else:
+            _check(lib().lbfv_step(self.h, int(scheme), int(n)), self.h)
 
     # ------------------------------------------------------------------ observables
     def moments(self):
@@ -357,6 +365,12 @@ class Batch:
         rho = np.zeros((ny, nx)); ux = np.zeros_like(rho); uy = np.zeros_like(rho)
         _check(lib().lbfv_batch_moments(self.h, int(i), _p(rho), _p(ux), _p(uy)), self.h)
         return rho, ux, uy
+
+    def nonfinite(self) -> np.ndarray:
+        """Per-case number of cells with a non-finite value (int32 [n])."""
+        out = np.zeros(len(self.shapes), dtype=np.int32)
+        _check(lib().lbfv_batch_nonfinite(self.h, out.ctypes.data_as(C.POINTER(C.c_int32))), self.h)
+        return out
 
     def set_shape(self, graph_steps: int = 0, rows: int = 0):
         _check(lib().lbfv_batch_set_shape(self.h, int(graph_steps), int(rows)), self.h)

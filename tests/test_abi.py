@@ -67,6 +67,7 @@ def test_null_pointers_are_rejected():
     assert lib.dugks_step(None, 1) == L.LBFV_EINVAL
     assert lib.bkg_step(None, 1) == L.LBFV_EINVAL
     assert lib.lbfv_batch_create(0, None, None, None, None) == L.LBFV_EINVAL
+    assert lib.lbfv_batch_nonfinite(None, None) == L.LBFV_EINVAL
 
 
 def test_state_errors_before_any_device_work():
@@ -87,6 +88,9 @@ def test_state_errors_before_any_device_work():
     assert L.lib().lbfv_set_periodic(ctx.h, 5) == L.LBFV_EINVAL
     assert L.lib().lbfv_set_tile(ctx.h, 8, 3) == L.LBFV_EINVAL
     assert L.lib().dugks_step(ctx.h, -1) == L.LBFV_EINVAL
+    assert L.lib().lbfv_step(ctx.h, 4, 1) == L.LBFV_EINVAL
+    assert L.lib().lbfv_step(ctx.h, -1, 1) == L.LBFV_EINVAL
+    assert L.lib().lbfv_step(ctx.h, L.LBFV_UPWIND, 1) == L.LBFV_ESTATE    # no state yet
     # replacing one side of a periodic axis leaves the other side unset
     L._check(L.lib().lbfv_set_wall(ctx.h, L.LBFV_WEST, 0.0, 0.0), ctx.h)
     assert L.lib().dugks_step(ctx.h, 1) == L.LBFV_ESTATE

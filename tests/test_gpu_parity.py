@@ -32,6 +32,19 @@ def rel(a, b):
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
 
 
+def assert_fp64(g, ref, ext, label):
+    """FP64 bar: rel L2 <= 1e-12 against the FP64 oracle; where the FP64 oracle's own
+    rounding has grown past 1e-13 (its distance from the extended-precision build of the
+    same oracle), the GPU must be as close to the extended result as the FP64 oracle is,
+    within a factor 2, or within 1e-12 of it."""
+    e, e_ora, e_gpu = rel(g, ref), rel(ref, ext), rel(g, ext)
+    print(f"{label}: GPU vs FP64 oracle {e:.2e}; vs extended: FP64 oracle {e_ora:.2e}, GPU {e_gpu:.2e}")
+    if e_ora <= 1e-13:
+        assert e < TOL64
+    else:
+        assert e_gpu <= max(TOL64, 2.0 * e_ora)
+
+
 def u_rel(ora, fa, fb):
     _, ua, va = ora.moments(fa)
     _, ub, vb = ora.moments(fb)
@@ -317,3 +330,72 @@ def test_taylor_green_4096_fp64_bench_shape(scheme, oscheme):
     print(f"tg4096 scheme={scheme} f {rel(g, ref):.2e} increment {e:.2e}")
     assert rel(g, ref) < TOL64
     assert e < 1e-9     # the 2-step increment itself, relative
+
+
+def test_batch_nonfinite_flags_match_oracle():
+    """Per-case non-finite check of the batch (the stability map's criterion) on 16^2
+    uniform cavities from rest after 3000 FP64 steps, against the oracle's outcome.
+    The points sit away from the stability limits: both schemes stable at CFL 0.5,
+    dt/tau 0.5 and CFL 1.0, dt/tau 5; BKG alone unstable at CFL 1.0, dt/tau 100; both
+    unstable at CFL 1.2, dt/tau 1000."""
+    n, steps = 16, 3000
+    points = [(0.5, 0.5), (1.0, 5.0), (1.0, 100.0), (1.2, 1000.0)]
+    expect = {O.DUGKS: [False, False, False, True], O.BKG: [False, False, True, True]}
+    xf = I.uniform_faces(n)
+    z = np.zeros((n, n))
+    bcs = [("wall", 0.0, 0.0), ("wall", 0.0, 0.0), ("wall", 0.0, 0.0), ("wall", 0.1, 0.0)]
+    cases = []
+    for cfl, r in points:
+        dt = I.cfl_dt(xf, xf, cfl)
+        cases.append(I.Workload(f"cav16_{cfl}_{r}", xf, xf.copy(), dt / r, dt, bcs, z + 1.0, z, z.copy()))
+    for scheme, oscheme in SCHEMES:
+        b = L.Batch(cases, compute=L.LBFV_FP64, storage=L.LBFV_STORE_NATIVE)
+        for i, w in enumerate(cases):
+            b.init_equilibrium(i, w.rho, w.ux, w.uy)
+        b.step(scheme, steps)
+        bad = b.nonfinite()
+        for i, w in enumerate(cases):
+            ora = oracle_case(w, 1)
+            f0 = ora.init_equilibrium(w.rho, w.ux, w.uy)
+            ref = ora.run(f0, oscheme, steps)
+            ora_bad = bool((~np.isfinite(ref)).any())
+            print(f"nonfinite scheme={scheme} case {w.name}: gpu {bad[i]} cells, oracle unstable {ora_bad}")
+            assert (bad[i] > 0) == ora_bad == expect[oscheme][i]
+            if not ora_bad:
+                ext = O.Case(w.xf, w.yf, w.rt, w.tau, w.dt, w.bcs, threads=1, extended=True).run(f0, oscheme, steps)
+                assert_fp64(b.get_f(i), ref, ext, w.name)
+        b.close()
+
+
+# ------------------------------------------------------------------ Sec. 2.4 interface values
+@pytest.mark.parametrize("scheme,oscheme", [(L.LBFV_CENTRAL, O.CENTRAL), (L.LBFV_UPWIND, O.UPWIND)])
+def test_collision_free_interface_values(scheme, oscheme):
+    """Central (Eq. cfd1) and upwind (Eq. cfd2) interface values through lbfv_step: the
+    ragged, stretched, all-boundary-kinds case in two launch shapes (FP64, bitwise equal
+    to each other), and Taylor-Green 32^2 for 1000 steps in FP64 and FP32 deviation
+    storage."""
+    w = _mixed_workload()
+    ora = oracle_case(w)
+    f0 = perturbed_state(ora, w, 5)
+    ref = ora.run(f0, oscheme, 40)
+    outs = []
+    for tile in ((5, 2), (37, 4)):
+        g = gpu_run(w, scheme, 40, f0, tile=tile)
+        print(f"sec2.4 scheme={scheme} mixed tile={tile} f {rel(g, ref):.2e}")
+        assert rel(g, ref) < TOL64
+        outs.append(g)
+    assert np.array_equal(outs[0], outs[1])
+    tg = I.taylor_green(32)
+    ora = oracle_case(tg, 1)
+    f0 = ora.init_equilibrium(tg.rho, tg.ux, tg.uy)
+    ref = ora.run(f0, oscheme, 1000)
+    g = gpu_run(tg, scheme, 1000)
+    # the central form amplifies rounding (forward-Euler transport): an FP64 perturbation
+    # of one ulp grows to ~2.5e-12 in 1000 steps, so the bar uses the extended oracle
+    ext = O.Case(tg.xf, tg.yf, tg.rt, tg.tau, tg.dt, tg.bcs, threads=1, extended=True).run(f0, oscheme, 1000)
+    assert_fp64(g, ref, ext, f"sec2.4 scheme={scheme} tg32")
+    g = gpu_run(tg, scheme, 1000, compute=L.LBFV_FP32, storage=L.LBFV_STORE_DEV_FP32)
+    e = u_rel(ora, g, ref)
+    print(f"sec2.4 scheme={scheme} tg32 fp32 u {e:.2e}")
+    assert e < TOL32_U
+

@@ -508,3 +508,160 @@ def test_table1_n32():
 @pytest.mark.slow
 def test_table1_n64():
     _check_table1(64, 4)
+
+
+# ------------------------------------------------------------------ Sec. 2.4 interface values
+def _nu_eff(w, c, scheme, f0, nsteps):
+    """Effective viscosity from the kinetic-energy decay exp(-4 nu k^2 t) of the
+    Taylor-Green vortex between two equal intervals (the first absorbs the initial layer)."""
+    f1 = c.run(f0, scheme, nsteps)
+    f2 = c.run(f1, scheme, nsteps)
+    ke = []
+    for f in (f1, f2):
+        _, u, v = c.moments(f)
+        ke.append(float((u * u + v * v).sum()))
+    return -math.log(ke[1] / ke[0]) / (4.0 * w.meta["k"] ** 2 * nsteps * w.dt)
+
+
+@pytest.mark.parametrize("cfl", [0.1, 0.4])
+def test_collision_free_interface_values_numerical_viscosity(cfl):
+    """Sec. 2.4: the upwind value of Eq. cfd2 ignores the collision along the half step,
+    so its face value carries an extra h f^(1) and the viscosity grows to (tau + dt/2) RT:
+    nu_eff/nu - 1 = dt/(2 tau) above DUGKS.  The central value of Eq. cfd1 also drops the
+    trace -h xi.grad f, which cancels that term to leading order: its viscosity carries
+    no dt/(2 tau) term (it differs from DUGKS by under 3 % of the upwind excess).
+    Taylor-Green 32^2, nu = 0.01, dt/tau = 0.46 and 1.85."""
+    w = I.taylor_green(32, cfl=cfl, nu=0.01)
+    c = O.Case(w.xf, w.yf, w.rt, w.tau, w.dt, w.bcs)
+    f0 = c.init_equilibrium(w.rho, w.ux, w.uy)
+    n = int(round(20.0 / w.dt))
+    nu = {s: _nu_eff(w, c, s, f0, n) / w.meta["nu"] for s in (O.DUGKS, O.UPWIND, O.CENTRAL)}
+    excess = w.dt / (2.0 * w.tau)
+    assert abs(nu[O.DUGKS] - 1.0) < 0.01
+    assert abs((nu[O.UPWIND] - nu[O.DUGKS]) / excess - 1.0) < 0.02
+    assert abs(nu[O.CENTRAL] - nu[O.DUGKS]) < 0.03 * excess     # no term of order dt/tau
+
+
+def test_collision_free_interface_values_invariants():
+    """Both Sec. 2.4 forms: equilibria stay fixed (periodic, inflow/outflow, closed box),
+    mass and momentum are conserved on a stretched periodic mesh, and in the
+    collisionless limit the upwind form is the BKG / DUGKS step itself."""
+    nx, ny = 10, 8
+    xf = I.tanh_faces(nx, 1.0); yf = I.geometric_faces(ny, 0.05, 1.0)
+    shape = (ny, nx)
+    rho0, u = 1.02, (0.03, -0.02)
+    inflow = ("inflow", rho0, u[0], u[1])
+    for bcs in (["periodic"] * 4, [inflow, ("outflow", 0), inflow, inflow]):
+        c = O.Case(xf, yf, RT, 0.01, I.cfl_dt(xf, yf, 0.5), bcs)
+        f = c.init_equilibrium(np.full(shape, rho0), np.full(shape, u[0]), np.full(shape, u[1]))
+        for scheme in (O.CENTRAL, O.UPWIND):
+            assert np.max(np.abs(c.run(f, scheme, 200) - f)) < 1e-14
+    c = O.Case(xf, yf, RT, 0.01, I.cfl_dt(xf, yf, 0.5), [("wall", 0.0, 0.0)] * 4)
+    f = c.init_equilibrium(np.ones(shape), np.zeros(shape), np.zeros(shape))
+    for scheme in (O.CENTRAL, O.UPWIND):
+        assert np.max(np.abs(c.run(f, scheme, 200) - f)) < 1e-15
+    xs, ys = I.tanh_faces(20, 1.5, 0.0, 1.0), I.tanh_faces(14, 0.8, 0.0, 0.7)
+    f = random_f(14, 20, 37, amp=0.05)
+    c = O.Case(xs, ys, RT, 0.05, 0.5 * I.cfl_dt(xs, ys, 1.0), ["periodic"] * 4)
+    t0 = c.totals(f)
+    for scheme in (O.CENTRAL, O.UPWIND):
+        t1 = c.totals(c.run(f, scheme, 100))
+        assert abs(t1[0] - t0[0]) / t0[0] < 1e-13
+        assert np.max(np.abs(t1[1:] - t0[1:])) / t0[0] < 1e-13
+    c = O.Case(xs, ys, RT, TAU_INF, 0.5 * I.cfl_dt(xs, ys, 1.0), ["periodic"] * 4)
+    up = c.run(f, O.UPWIND, 20)
+    assert np.array_equal(up, c.run(f, O.BKG, 20))
+    assert rel(up, c.run(f, O.DUGKS, 20)) < 1e-15
+    assert rel(c.run(f, O.CENTRAL, 20), up) > 1e-6     # the trace matters
+
+
+# ------------------------------------------------------------------ symmetry sides (Sec. 3.3)
+MIRROR_Y = [0, 1, 4, 3, 2, 8, 7, 6, 5]     # e_y -> -e_y in the Sec. 2.1 direction order
+MIRROR_X = [0, 3, 2, 1, 4, 6, 5, 8, 7]     # e_x -> -e_x
+
+
+def _mirror_pin(axis, other_bcs, scheme, nsteps=25):
+    """A doubly periodic domain of twice the height (or width), holding a state that is
+    mirror symmetric about its mid-plane, against the half domain with two symmetry
+    sides: the half must evolve exactly as the upper (right) half of the whole."""
+    n_half, n_other = 7, 9
+    half = I.tanh_faces(n_half, 1.1, 0.0, 0.6)                  # stretched, [0, 0.6]
+    full = np.concatenate([-half[::-1], half[1:]])
+    other = I.tanh_faces(n_other, 0.9, 0.0, 1.0)
+    g = random_f(n_other, n_half, 53, amp=0.1) if axis == 1 else random_f(n_half, n_other, 53, amp=0.1)
+    mir = MIRROR_Y if axis == 1 else MIRROR_X
+    if axis == 1:                                                # y mirrored: [9, 2*n_half, n_other]
+        g = random_f(n_half, n_other, 53, amp=0.1)
+        low = g[mir][:, ::-1, :]
+        f_full = np.concatenate([low, g], axis=1)
+        c_full = O.Case(other, full, RT, 0.02, 0.7 * I.cfl_dt(other, full, 1.0), other_bcs + ["periodic"] * 2)
+        c_half = O.Case(other, half, RT, 0.02, 0.7 * I.cfl_dt(other, full, 1.0), other_bcs + ["symmetry"] * 2)
+        up = c_full.run(f_full, scheme, nsteps)[:, n_half:, :]
+    else:                                                        # x mirrored: [9, n_other, 2*n_half]
+        g = random_f(n_other, n_half, 53, amp=0.1)
+        low = g[mir][:, :, ::-1]
+        f_full = np.concatenate([low, g], axis=2)
+        c_full = O.Case(full, other, RT, 0.02, 0.7 * I.cfl_dt(full, other, 1.0), ["periodic"] * 2 + other_bcs)
+        c_half = O.Case(half, other, RT, 0.02, 0.7 * I.cfl_dt(full, other, 1.0), ["symmetry"] * 2 + other_bcs)
+        up = c_full.run(f_full, scheme, nsteps)[:, :, n_half:]
+    return rel(c_half.run(g, scheme, nsteps), up)
+
+
+@pytest.mark.parametrize("scheme", [O.DUGKS, O.BKG, O.UPWIND])
+def test_symmetry_side_equals_mirrored_whole_domain(scheme):
+    """Specular symmetry sides (Sec. 3.3) on stretched meshes, with periodic and with
+    moving-wall / inflow-outflow sides across them (corners included)."""
+    # the other sides must be mirror symmetric themselves: wall and inflow velocities
+    # along the axis that is not mirrored
+    others = {0: (["periodic"] * 2, [("wall", 0.0, 0.01), ("wall", 0.0, -0.02)],
+                  [("inflow", 1.0, 0.0, 0.02), ("outflow", 1)]),
+              1: (["periodic"] * 2, [("wall", 0.01, 0.0), ("wall", -0.02, 0.0)],
+                  [("inflow", 1.0, 0.02, 0.0), ("outflow", 1)])}
+    for axis in (0, 1):
+        for other in others[axis]:
+            assert _mirror_pin(axis, list(other), scheme) < 1e-14, (axis, other)
+
+
+def test_wall_segment_of_a_side():
+    """A south side that is a symmetry plane up to cell i0 and a no-slip wall from there
+    on (the flat-plate layout of Sec. 3.3): i0 = 0 is the whole-side wall bit for bit;
+    the split box conserves mass and keeps a rest state; far from the split (beyond the
+    k-cell reach of k steps) the two parts match the whole-side symmetry and wall runs."""
+    nx, ny, k = 24, 10, 5
+    xf = I.tanh_faces(nx, 0.8, 0.0, 2.0); yf = I.geometric_faces(ny, 0.03, 1.0)
+    dt = I.cfl_dt(xf, yf, 0.5)
+    f = random_f(ny, nx, 61, amp=0.05)
+    north, west, east = ("wall", 0.03, 0.0), ("inflow", 1.0, 0.03, 0.0), ("outflow", 0)
+    for scheme in (O.DUGKS, O.BKG):
+        whole = O.Case(xf, yf, RT, 0.01, dt, [west, east, ("wall", 0.01, 0.0), north]).run(f, scheme, k)
+        seg0 = O.Case(xf, yf, RT, 0.01, dt, [west, east, ("wall_from", 0, 0.01, 0.0, "symmetry"), north])
+        assert np.array_equal(seg0.run(f, scheme, k), whole)
+        sym = O.Case(xf, yf, RT, 0.01, dt, [west, east, "symmetry", north]).run(f, scheme, k)
+        i0 = 12
+        split = O.Case(xf, yf, RT, 0.01, dt, [west, east, ("wall_from", i0, 0.01, 0.0, "symmetry"), north])
+        g = split.run(f, scheme, k)
+        assert np.array_equal(g[:, :, : i0 - k - 1], sym[:, :, : i0 - k - 1])
+        assert np.array_equal(g[:, :, i0 + k + 1:], whole[:, :, i0 + k + 1:])
+        assert rel(g[:, :, i0 - 1: i0 + 1], sym[:, :, i0 - 1: i0 + 1]) > 1e-8   # the split is felt
+        box = O.Case(xf, yf, RT, 0.01, dt, [("wall", 0.0, 0.0), ("wall", 0.0, 0.0),
+                                           ("wall_from", i0, 0.02, 0.0, "symmetry"), ("wall", 0.0, 0.0)])
+        t0 = box.totals(f)
+        assert abs(box.totals(box.run(f, scheme, 200))[0] - t0[0]) / t0[0] < 1e-13
+        rest = box.init_equilibrium(np.ones((ny, nx)), np.zeros((ny, nx)), np.zeros((ny, nx)))
+        still = O.Case(xf, yf, RT, 0.01, dt, [("wall", 0.0, 0.0), ("wall", 0.0, 0.0),
+                                             ("wall_from", i0, 0.0, 0.0, "symmetry"), ("wall", 0.0, 0.0)])
+        assert np.max(np.abs(still.run(rest, scheme, 100) - rest)) < 1e-15
+
+
+def test_extended_precision_build_is_the_same_algorithm():
+    """The oracle's extended-precision build (the reference that sizes FP64 rounding on
+    ill-conditioned runs) computes the same step: on a well-conditioned mixed case both
+    builds agree to 1e-14 after 30 steps of every scheme, yet are not bit-identical."""
+    xf = I.tanh_faces(29, 1.2, 0.0, 2.0); yf = I.geometric_faces(17, 0.02, 1.0)
+    f = random_f(17, 29, 71, amp=0.1)
+    bcs = [("inflow", 1.0, 0.03, 0.01), ("outflow", 1), ("wall_from", 9, 0.01, 0.0, "symmetry"), ("wall", 0.02, 0.0)]
+    dt = O.dt_from_cfl(xf, yf, RT, 0.6)
+    for scheme in (O.DUGKS, O.BKG, O.CENTRAL, O.UPWIND):
+        a = O.Case(xf, yf, RT, 0.01, dt, bcs).run(f, scheme, 30)
+        b = O.Case(xf, yf, RT, 0.01, dt, bcs, extended=True).run(f, scheme, 30)
+        assert 0.0 < rel(a, b) < 1e-14
