@@ -54,6 +54,10 @@ def parse():
                    help="instead of the throughput benchmark: the stable band of dt/tau against CFL for "
                         "the uniform 32^2 and 64^2 cavity, both schemes, one batch per scheme")
     p.add_argument("--map-steps", type=int, default=20000, help="steps after which a case counts as stable")
+    p.add_argument("--boundary-layer-paper", action="store_true",
+                   help="instead of the throughput benchmark: the flat plate of Sec. 3.3 on the paper's "
+                        "meshes, both schemes, profiles against the Blasius solution")
+    p.add_argument("--flow-throughs", type=float, default=4.0, help="run length of the flat plate, in L / U0")
     p.add_argument("--scheme", default="dugks", choices=["dugks", "bkg"])
     p.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     p.add_argument("--target", type=float, default=1e-8, help="residual target (per 1000 steps)")
@@ -263,6 +267,51 @@ def stability_map(a, stream):
     return out
 
 
+def boundary_layer_paper(a, stream):
+    """Sec. 3.3: laminar flat plate at Re_L = 1e5 on the paper's meshes (dy_min 0.1, 0.05,
+    0.02; CFL 0.5), DUGKS and BKG in FP64 from the uniform free stream for a fixed number
+    of flow-through times; u / U0 and v / (U0 / (2 sqrt(Re_x))) at the two stations of the
+    paper against the Blasius solution at the cell centres with eta <= 8."""
+    import torch
+    from paper_1511_00242_amd import inputs as I
+    from paper_1511_00242_amd import lbfv as L
+    eta_b, u_b, v_b, _ = I.blasius()
+    out = {"workload": "flat_plate_paper_mesh_re1e5", "flow_throughs": a.flow_throughs, "cases": {}}
+    t0 = time.perf_counter()
+    for dy in (0.1, 0.05, 0.02):
+        w = I.boundary_layer_paper(dy)
+        steps = int(round(a.flow_throughs * w.meta["length"] / w.meta["u0"] / w.dt))
+        for sname, scheme in (("dugks", L.LBFV_DUGKS), ("bkg", L.LBFV_BKG)):
+            ctx = L.Context(w.xf, w.yf, w.tau, w.dt, bcs=w.bcs, check_every=10000, stream=stream.cuda_stream)
+            ctx.init_equilibrium(w.rho, w.ux, w.uy)
+            ctx.step(scheme, steps - 1000)
+            ctx.residual()
+            ctx.step(scheme, 1000)
+            res = ctx.residual()
+            _, ux, uy = ctx.moments()
+            ctx.close()
+            yc = 0.5 * (w.yf[1:] + w.yf[:-1])
+            xc = 0.5 * (w.xf[1:] + w.xf[:-1])
+            case = {"steps": steps, "dt_over_tau": w.dt / w.tau, "residual_per_1000": res,
+                    "cells": [w.nx, w.ny]}
+            for st, i in (("x1", 40 + 29), ("x2", 40 + 50)):
+                x = xc[i]
+                eta = yc * math.sqrt(w.meta["u0"] / (w.meta["nu"] * x))
+                vs = w.meta["u0"] / (2.0 * math.sqrt(w.meta["u0"] * x / w.meta["nu"]))
+                m = eta <= 8.0
+                du = ux[m, i] / w.meta["u0"] - np.interp(eta[m], eta_b, u_b)
+                dv = uy[m, i] / vs - np.interp(eta[m], eta_b, v_b)
+                case[st] = {"x": x, "cells_in_eta8": int(m.sum()),
+                            "cells_in_layer": int((eta <= 4.91).sum()),
+                            "u_rms_err": float(np.sqrt(np.mean(du ** 2))), "u_max_err": float(np.max(np.abs(du))),
+                            "v_rms_err": float(np.sqrt(np.mean(dv ** 2))), "v_max_err": float(np.max(np.abs(dv)))}
+            out["cases"][f"{sname}_dy{dy:g}"] = case
+            print(f"[flat plate] {sname} dy_min {dy}: {steps} steps, residual {res:.2e}, "
+                  f"u rms err x1 {case['x1']['u_rms_err']:.4f} x2 {case['x2']['u_rms_err']:.4f} "
+                  f"({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
+    return out
+
+
 def profiled_traffic(tile, ms_per_step):
     """HBM traffic of the headline kernel from the committed rocprofv3 counter summary:
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the same counters read for a
@@ -315,6 +364,9 @@ def main():
     stream = torch.cuda.current_stream()
     if a.stability_map:
         print(json.dumps(stability_map(a, stream)), flush=True)
+        return
+    if a.boundary_layer_paper:
+        print(json.dumps(boundary_layer_paper(a, stream)), flush=True)
         return
     if a.cavity_residual:
         print(json.dumps(cavity_residual(a, stream)), flush=True)

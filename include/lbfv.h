@@ -15,7 +15,8 @@
  * Both schemes track the same variable f~, so a state may be advanced by either.
  * Boundary conditions (Sec. 2.5, Sec. 3.3): periodic, half-way bounce-back of a
  * moving no-slip wall with ghost cells by linear extrapolation, equilibrium
- * (free-stream) inflow, zero- or first-order extrapolation outflow.
+ * (free-stream) inflow, zero- or first-order extrapolation outflow, symmetry planes, and a
+ * wall segment ending a south / north side (Sec. 3.3).
  *
  * Conventions for every function:
  *   - returns LBFV_OK (0) or a negative lbfv_status; nothing is thrown across the ABI;
@@ -113,6 +114,17 @@ int lbfv_set_wall(lbfv_ctx *ctx, int side, double uwx, double uwy);
 int lbfv_set_inflow_eq(lbfv_ctx *ctx, int side, double rho, double ux, double uy);
 /* Outflow: ghost cells copy the adjacent cell (order 0) or extrapolate linearly (order 1). */
 int lbfv_set_outflow_extrap(lbfv_ctx *ctx, int side, int order);
+/* Symmetry plane (Sec. 3.3: the section of the flat-plate domain's lower side ahead of the
+ * plate): specular reflection.  Ghost cells hold the adjacent cell's value of the mirrored
+ * direction (normal component reversed), and on the side's faces the incoming values are
+ * the outgoing ones mirrored, so no mass crosses. */
+int lbfv_set_symmetry(lbfv_ctx *ctx, int side);
+/* No-slip wall segment at the end of a south or north side (Sec. 3.3: the plate starts at
+ * its leading edge): cells first_cell..nx-1 of the side are a half-way bounce-back wall
+ * moving with (uwx, uwy); the cells before it keep the side's kind, which must already be
+ * set and not periodic (else EINVAL).  Setting the side's kind again removes the segment.
+ * EINVAL also for an x-side, first_cell outside [0, nx) or a non-finite velocity. */
+int lbfv_set_wall_from(lbfv_ctx *ctx, int side, int32_t first_cell, double uwx, double uwy);
 
 /* State.  f~ of an equilibrium state is feq (Omega(feq) = 0). */
 int lbfv_init_equilibrium(lbfv_ctx *ctx, const double *rho, const double *ux, const double *uy);
@@ -172,7 +184,7 @@ const char *lbfv_last_error(const lbfv_ctx *ctx);   /* ctx NULL: last error of t
  * list of (case, strip, row block) items; lbfv_batch_step replays a HIP graph of
  * K such launches.  Compute / storage follow opts (FP32 deviation storage is the
  * intended use).  bc_kind per side: 0 periodic, 1 wall (bc_val = uwx, uwy),
- * 2 inflow (rho, ux, uy), 3 outflow (order). */
+ * 2 inflow (rho, ux, uy), 3 outflow (order), 4 symmetry. */
 typedef struct {
     lbfv_mesh mesh;
     double tau, dt;

@@ -24,7 +24,7 @@
 
 namespace lbfv {
 
-enum { BC_PERIODIC = 0, BC_WALL = 1, BC_INFLOW = 2, BC_OUTFLOW = 3 };
+enum { BC_PERIODIC = 0, BC_WALL = 1, BC_INFLOW = 2, BC_OUTFLOW = 3, BC_SYMMETRY = 4 };
 enum { SIDE_W = 0, SIDE_E = 1, SIDE_S = 2, SIDE_N = 3 };
 // Kernel forms: DUGKS and BKG.  The collision-free face values of Sec. 2.4 (central,
 // Eq. cfd1; upwind, Eq. cfd2) run the DUGKS kernel with phi = f, no face back-transform
@@ -35,6 +35,9 @@ enum { SCHEME_DUGKS = 0, SCHEME_BKG = 1, SCHEME_CENTRAL = 2, SCHEME_UPWIND = 3 }
 constexpr int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 constexpr int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 constexpr int REV[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+// mirror images across a plane normal to x (e_x -> -e_x) and to y (e_y -> -e_y)
+constexpr int MIRX[9] = {0, 3, 2, 1, 4, 6, 5, 8, 7};
+constexpr int MIRY[9] = {0, 1, 4, 3, 2, 8, 7, 6, 5};
 __host__ __device__ constexpr double wgt(int a) { return a == 0 ? 4.0 / 9.0 : (a < 5 ? 1.0 / 9.0 : 1.0 / 36.0); }
 __host__ __device__ constexpr double inv_wgt(int a) { return a == 0 ? 2.25 : (a < 5 ? 9.0 : 36.0); }
 
@@ -52,6 +55,8 @@ struct StepParams {
     const T *xm, *ym;       // metric arrays (see above)
     int32_t bc[4];          // boundary kind per side W, E, S, N
     T bcv[4][3];            // wall: 6 U_w / c (x, y); inflow: rho, ux / c, uy / c; outflow: order
+    int32_t wfrom[4];       // south / north: first cell of a no-slip wall segment (-1: none)
+    T wsv[4][2];            // that segment's 6 U_w / c
     T ext[4];               // linear ghost extrapolation factor per side
     T rho0;                 // deviation reference density (0: plain storage)
     T hc;                   // h c, h = dt / 2
@@ -237,6 +242,7 @@ struct March {
     int64_t lslot, sslot;      // storage slot this lane loads / stores
     bool per_x, per_y;
     bool ghostW, ghostE;       // this wave holds the west / east ghost column
+    bool segS, segN;           // this lane's column lies in the south / north wall segment
     int laneE;                 // lane of column nx
     // per-lane face/cell coefficients
     T cEm, cE0, cEp, sLE;      // east face: c = lam - e_x hc id for e_x = -1, 0, +1; hc (1 - lam)
@@ -259,6 +265,8 @@ struct March {
         // slots: the wave writes its 64-slot block whole (pad values are never read)
         sslot = (int64_t)(x0 / STRIP) * SLOTS + (lane == 0 ? STRIP : (lane == 63 ? STRIP + 1 : lane - 1));
         ghostW = BND && !per_x && x0 == 0;
+        segS = BND && P.wfrom[SIDE_S] >= 0 && col >= P.wfrom[SIDE_S];
+        segN = BND && P.wfrom[SIDE_N] >= 0 && col >= P.wfrom[SIDE_N];
         laneE = nx - x0 + 1;
         ghostE = BND && !per_x && laneE <= 63;
         const T *lam = P.xm, *id = P.xm + (nx + 1), *is = P.xm + 2 * (nx + 1), *cd = is + nx;
@@ -315,10 +323,12 @@ struct March {
         }
     }
 
-    // ---- ghost cells (Sec. 2.5, readings R5 / R6): one ghost value per direction from
-    // the two nearest interior values g1 (adjacent) and g2 (next).
-    __device__ __forceinline__ T ghost_rule(int A, int side, T g1, T g2) const {
+    // ---- ghost cells (Sec. 2.5, readings R5 / R6 / R17): one ghost value per direction
+    // from the two nearest interior values g1 (adjacent) and g2 (next) of that direction,
+    // or gm, the adjacent value of the mirrored direction (symmetry side).
+    __device__ __forceinline__ T ghost_rule(int A, int side, T g1, T g2, T gm) const {
         const int k = P.bc[side];
+        if (k == BC_SYMMETRY) return gm;
         if (k == BC_INFLOW) {
             const T rho = P.bcv[side][0], ux = P.bcv[side][1], uy = P.bcv[side][2];
             return dfeq(A, rho - P.rho0, rho, rho * ux, rho * uy, ux, uy, usq_term(ux, uy));
@@ -328,11 +338,13 @@ struct March {
     }
     // x-side ghost lanes of one row (x-sides first, as in Sec. 2.5 reading R5)
     __device__ __forceinline__ void ghost_x(T (&phi)[9]) const {
+        // only the ghost lane is written, and it reads its interior neighbours, so the
+        // directions may be filled in place in any order
         if (ghostW) {
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
                 T g1 = shl1(phi[a]), g2 = shl1(g1);
-                T g = ghost_rule(a, SIDE_W, g1, g2);
+                T g = ghost_rule(a, SIDE_W, g1, g2, shl1(phi[MIRX[a]]));
                 phi[a] = lane == 0 ? g : phi[a];
             }
         }
@@ -340,16 +352,19 @@ struct March {
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
                 T g1 = shr1(phi[a]), g2 = shr1(g1);
-                T g = ghost_rule(a, SIDE_E, g1, g2);
+                T g = ghost_rule(a, SIDE_E, g1, g2, shr1(phi[MIRX[a]]));
                 phi[a] = lane == laneE ? g : phi[a];
             }
         }
     }
-    // y-side ghost row from rows r1 (adjacent) and r2 (next); ghost lanes included (corners)
+    // y-side ghost row from rows r1 (adjacent) and r2 (next); ghost lanes included (corners).
+    // Lanes in the side's wall segment take the wall rule.
     __device__ __forceinline__ void ghost_y(int side, const T (&r1)[9], const T (&r2)[9], T (&out)[9]) const {
+        const bool seg = side == SIDE_S ? segS : segN;
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
-            out[a] = ghost_rule(a, side, r1[a], r2[a]);
+            const T g = ghost_rule(a, side, r1[a], r2[a], r1[MIRY[a]]);
+            out[a] = seg ? fma(r1[a] - r2[a], P.ext[side], r1[a]) : g;
         }
     }
 
@@ -363,6 +378,19 @@ struct March {
             if (EX[a] * NX + EY[a] * NY > 0) {
                 const T v = fma(-(T)wgt(a), edot<T>(a, bx, by), fb[a]);
                 fb[REV[a]] = on ? v : fb[REV[a]];
+            }
+        }
+    }
+
+    // ---- symmetry face (reading R17): specular reflection, the mirrored direction of
+    // every direction leaving the fluid takes its value
+    template <int NX, int NY>
+    __device__ __forceinline__ void specular(T (&fb)[9], bool on) const {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            if (EX[a] * NX + EY[a] * NY > 0) {
+                const int m = NX != 0 ? MIRX[a] : MIRY[a];
+                fb[m] = on ? fb[a] : fb[m];
             }
         }
     }
@@ -443,14 +471,20 @@ struct March {
         xface(P0, sy, fW);
         if (ghostW && P.bc[SIDE_W] == BC_WALL)
             bounce<-1, 0>(fW, P.bcv[SIDE_W][0], P.bcv[SIDE_W][1], lane == 1);
+        if (ghostW && P.bc[SIDE_W] == BC_SYMMETRY) specular<-1, 0>(fW, lane == 1);
         if (ghostE && P.bc[SIDE_E] == BC_WALL)
             bounce<1, 0>(fW, P.bcv[SIDE_E][0], P.bcv[SIDE_E][1], lane == laneE);
+        if (ghostE && P.bc[SIDE_E] == BC_SYMMETRY) specular<1, 0>(fW, lane == laneE);
         face_mix<0>(fW);
 
         // y-face north of row k
         T fN[9];
         yface(k + 1, P0, Pp, fN);
-        if (BND && k + 1 == ny && P.bc[SIDE_N] == BC_WALL) bounce<0, 1>(fN, P.bcv[SIDE_N][0], P.bcv[SIDE_N][1], true);
+        if (BND && k + 1 == ny) {
+            if (P.bc[SIDE_N] == BC_WALL) bounce<0, 1>(fN, P.bcv[SIDE_N][0], P.bcv[SIDE_N][1], !segN);
+            if (P.bc[SIDE_N] == BC_SYMMETRY) specular<0, 1>(fN, !segN);
+            if (P.wfrom[SIDE_N] >= 0) bounce<0, 1>(fN, P.wsv[SIDE_N][0], P.wsv[SIDE_N][1], segN);
+        }
         face_mix<1>(fN);
 
         // flux divergence and update, Eq. eq_update with the sign of Eq. bkg_fv (reading R1)
@@ -512,7 +546,11 @@ struct March {
             }
         }
         yface(j0, PA, PB, fS);
-        if (BND && j0 == 0 && P.bc[SIDE_S] == BC_WALL) bounce<0, -1>(fS, P.bcv[SIDE_S][0], P.bcv[SIDE_S][1], true);
+        if (BND && j0 == 0) {
+            if (P.bc[SIDE_S] == BC_WALL) bounce<0, -1>(fS, P.bcv[SIDE_S][0], P.bcv[SIDE_S][1], !segS);
+            if (P.bc[SIDE_S] == BC_SYMMETRY) specular<0, -1>(fS, !segS);
+            if (P.wfrom[SIDE_S] >= 0) bounce<0, -1>(fS, P.wsv[SIDE_S][0], P.wsv[SIDE_S][1], segS);
+        }
         face_mix<1>(fS);
 
         for (int k = j0; k < j1; k += 3) {

@@ -28,6 +28,8 @@ struct HostCase {
     double rt = 1.0 / 3.0, c = 1.0, tau = 1.0, dt = 1.0;
     int bc[4] = {-1, -1, -1, -1};
     double bcval[4][3] = {};
+    int wfrom[4] = {-1, -1, -1, -1};   // south / north wall segment: first cell, or -1
+    double wsv[4][2] = {};             // the segment's wall velocity
     int variant = V_F64;
     double rho0 = 0.0;        // 0 for native storage
     int64_t pitch = 0, plane = 0;
@@ -169,6 +171,9 @@ StepParams<T> make_params(const HostCase &h, double ext[4], int scheme = SCHEME_
         } else if (h.bc[s] == BC_OUTFLOW) {
             P.bcv[s][0] = (T)h.bcval[s][0];
         }
+        P.wfrom[s] = h.wfrom[s];
+        P.wsv[s][0] = (T)(6.0 * h.wsv[s][0] / h.c);
+        P.wsv[s][1] = (T)(6.0 * h.wsv[s][1] / h.c);
     }
     const double tau = h.tau, dt = h.dt, hh = 0.5 * dt;
     P.rho0 = (T)h.rho0;
@@ -441,6 +446,7 @@ int set_side(HostCase &h, int side, int kind, double a, double b, double c) {
     const int other = side ^ 1;
     if (h.bc[side] == BC_PERIODIC && kind != BC_PERIODIC && h.bc[other] == BC_PERIODIC) h.bc[other] = -1;
     h.bc[side] = kind;
+    h.wfrom[side] = -1;       // a new kind replaces the whole side
     h.bcval[side][0] = a;
     h.bcval[side][1] = b;
     h.bcval[side][2] = c;
@@ -768,6 +774,28 @@ int lbfv_set_inflow_eq(lbfv_ctx *c, int side, double rho, double ux, double uy) 
     if (side < 0 || side > 3 || !(rho > 0) || !std::isfinite(ux) || !std::isfinite(uy))
         return c->fail(LBFV_EINVAL, "lbfv_set_inflow_eq: bad side or state");
     return set_side(c->hc, side, BC_INFLOW, rho, ux, uy);
+}
+
+int lbfv_set_symmetry(lbfv_ctx *c, int side) {
+    if (!c) return LBFV_EINVAL;
+    if (side < 0 || side > 3) return c->fail(LBFV_EINVAL, "lbfv_set_symmetry: bad side");
+    return set_side(c->hc, side, BC_SYMMETRY, 0, 0, 0);
+}
+
+int lbfv_set_wall_from(lbfv_ctx *c, int side, int32_t first_cell, double uwx, double uwy) {
+    if (!c) return LBFV_EINVAL;
+    HostCase &h = c->hc;
+    if (side != LBFV_SOUTH && side != LBFV_NORTH)
+        return c->fail(LBFV_EINVAL, "lbfv_set_wall_from: only the south and north sides take a wall segment");
+    if (first_cell < 0 || first_cell >= h.nx || !std::isfinite(uwx) || !std::isfinite(uwy))
+        return c->fail(LBFV_EINVAL, "lbfv_set_wall_from: bad first cell or velocity");
+    if (h.bc[side] < 0 || h.bc[side] == BC_PERIODIC)
+        return c->fail(LBFV_EINVAL, "lbfv_set_wall_from: set a non-periodic kind on the side first");
+    h.wfrom[side] = first_cell;
+    h.wsv[side][0] = uwx;
+    h.wsv[side][1] = uwy;
+    h.metrics_dirty = true;
+    return LBFV_OK;
 }
 
 int lbfv_set_outflow_extrap(lbfv_ctx *c, int side, int order) {
@@ -1312,7 +1340,7 @@ int lbfv_batch_create(int32_t n, const lbfv_case *cs, const lbfv_velset *vel, co
             return st;
         }
         for (int s = 0; s < 4; ++s)
-            if (cs[i].bc_kind[s] < 0 || cs[i].bc_kind[s] > 3) {
+            if (cs[i].bc_kind[s] < 0 || cs[i].bc_kind[s] > BC_SYMMETRY) {
                 g_last_error = "lbfv_batch_create: bad boundary kind";
                 return LBFV_EINVAL;
             }

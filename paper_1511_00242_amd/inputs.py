@@ -8,8 +8,13 @@ the GPU library and the CPU oracle receive as inputs, so the two sides start
 from identical data.  Fields are numpy float64, shaped ``[ny, nx]``.
 
 Boundary sides are listed in the order (west, east, south, north):
-``"periodic"``, ``("wall", uwx, uwy)``, ``("inflow", rho, ux, uy)`` or
-``("outflow", order)``.
+``"periodic"``, ``("wall", uwx, uwy)``, ``("inflow", rho, ux, uy)``,
+``("outflow", order)``, ``"symmetry"``, or on the south / north side
+``("wall_from", i0, uwx, uwy, before)``: a no-slip wall from cell i0 on, the cells
+before it of kind ``before``.
+
+The Blasius similarity solution (the flat-plate reference of Sec. 3.3) is here too:
+like the Taylor-Green field it is an analytic reference, not part of the schemes.
 """
 from __future__ import annotations
 
@@ -204,6 +209,73 @@ def boundary_layer(nx=512, ny=256, *, length=94.76, u_inf=0.1, re_l=1e5, first=N
                      ("inflow", 1.0, u_inf, 0.0)],
                     np.ones(shape), np.full(shape, u_inf), np.zeros(shape), rt,
                     dict(u_inf=u_inf, nu=nu, re_l=re_l))
+
+
+def boundary_layer_paper(dy_min=0.1, *, u0=0.1, length=94.76, re_l=1e5, cfl=0.5, rt=RT,
+                         name=None) -> Workload:
+    """The flat-plate mesh of Sec. 3.3.  x: 40 cells ahead of the plate growing upstream
+    by 1.1 and 80 cells on the plate growing downstream by 1.05, both from 0.1 at the
+    leading edge (x = 0); the plate length L = 94.76 is the centre of the last plate
+    cell, and the two profile stations 6.4381 and 21.5082 are the centres of plate
+    cells 29 and 50.  y: growing by 1.1 from dy_min, as many cells as make the height
+    pass 50.  Sides: free stream (equilibrium) on the west and north, zero-order outflow
+    on the east, symmetry ahead of the plate and the no-slip plate on the south.
+    Re = U0 L / nu = 1e5; uniform free stream at start."""
+    up = 0.1 * 1.1 ** np.arange(40)
+    down = 0.1 * 1.05 ** np.arange(80)
+    xf = np.concatenate([-np.cumsum(up)[::-1], [0.0], np.cumsum(down)])
+    ny = 1
+    while dy_min * (1.1 ** ny - 1.0) / 0.1 <= 50.0:
+        ny += 1
+    yf = np.concatenate([[0.0], np.cumsum(dy_min * 1.1 ** np.arange(ny))])
+    nu = u0 * length / re_l
+    tau = nu / rt
+    dt = cfl_dt(xf, yf, cfl, rt)
+    nx = len(xf) - 1
+    shape = (ny, nx)
+    stations = {"x1": 0.5 * (xf[40 + 29] + xf[40 + 30]), "x2": 0.5 * (xf[40 + 50] + xf[40 + 51])}
+    return Workload(name or f"boundary_layer_paper_dy{dy_min:g}", xf, yf, tau, dt,
+                    [("inflow", 1.0, u0, 0.0), ("outflow", 0), ("wall_from", 40, 0.0, 0.0, "symmetry"),
+                     ("inflow", 1.0, u0, 0.0)],
+                    np.ones(shape), np.full(shape, u0), np.zeros(shape), rt,
+                    dict(u0=u0, nu=nu, re_l=re_l, length=length, dy_min=dy_min, plate_first_cell=40,
+                         stations=stations))
+
+
+def blasius(eta_max=12.0, n=6001):
+    """Blasius similarity solution of the flat plate: F''' + F F'' / 2 = 0 with
+    F(0) = F'(0) = 0 and F'(inf) = 1, by shooting on F''(0) (bisection) with classical
+    fourth-order Runge-Kutta on a uniform grid of eta = y sqrt(U0 / (nu x)).
+    Returns (eta, u / U0 = F', v / (U0 / (2 sqrt(Re_x))) = eta F' - F, F''(0))."""
+    eta = np.linspace(0.0, eta_max, n)
+    h = eta[1] - eta[0]
+
+    def rhs(y):
+        return np.array([y[1], y[2], -0.5 * y[0] * y[2]])
+
+    def shoot(s):
+        y = np.array([0.0, 0.0, s])
+        out = np.empty((n, 3))
+        out[0] = y
+        for k in range(1, n):
+            k1 = rhs(y)
+            k2 = rhs(y + 0.5 * h * k1)
+            k3 = rhs(y + 0.5 * h * k2)
+            k4 = rhs(y + h * k3)
+            y = y + h / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4)
+            out[k] = y
+        return out
+
+    lo, hi = 0.1, 1.0
+    for _ in range(50):
+        mid = 0.5 * (lo + hi)
+        if shoot(mid)[-1, 1] > 1.0:
+            hi = mid
+        else:
+            lo = mid
+    s = 0.5 * (lo + hi)
+    sol = shoot(s)
+    return eta, sol[:, 1], eta * sol[:, 1] - sol[:, 0], s
 
 
 # ----------------------------------------------------------------------------- batch draw

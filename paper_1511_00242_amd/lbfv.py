@@ -29,7 +29,8 @@ LBFV_STORE_NATIVE, LBFV_STORE_DEV_FP32, LBFV_STORE_DEV_BF16, LBFV_STORE_DEV_FP16
 # every function the header declares
 EXPORTS = (
     "lbfv_create", "lbfv_destroy", "lbfv_dt_from_cfl", "lbfv_set_periodic", "lbfv_set_wall",
-    "lbfv_set_inflow_eq", "lbfv_set_outflow_extrap", "lbfv_init_equilibrium",
+    "lbfv_set_inflow_eq", "lbfv_set_outflow_extrap", "lbfv_set_symmetry", "lbfv_set_wall_from",
+    "lbfv_init_equilibrium",
     "lbfv_init_chapman_enskog", "lbfv_set_f",
     "lbfv_get_f", "lbfv_bind_buffers", "lbfv_required_bytes", "dugks_step", "bkg_step", "lbfv_step",
     "lbfv_moments", "lbfv_totals", "lbfv_residual", "lbfv_set_tile", "lbfv_get_tile",
@@ -89,6 +90,8 @@ def lib():
             "lbfv_set_wall": ([vp, ip, C.c_double, C.c_double], ip),
             "lbfv_set_inflow_eq": ([vp, ip, C.c_double, C.c_double, C.c_double], ip),
             "lbfv_set_outflow_extrap": ([vp, ip, ip], ip),
+            "lbfv_set_symmetry": ([vp, ip], ip),
+            "lbfv_set_wall_from": ([vp, ip, C.c_int32, C.c_double, C.c_double], ip),
             "lbfv_init_equilibrium": ([vp, dp, dp, dp], ip),
             "lbfv_init_chapman_enskog": ([vp, dp, dp, dp, dp, dp, dp], ip),
             "lbfv_set_f": ([vp, dp], ip),
@@ -138,10 +141,14 @@ def _check(status: int, handle=None):
                         if isinstance(msg, bytes) else str(msg))
 
 
-_KIND = {"periodic": 0, "wall": 1, "inflow": 2, "outflow": 3}
+_KIND = {"periodic": 0, "wall": 1, "inflow": 2, "outflow": 3, "symmetry": 4}
 
 
 def _side(spec):
+    """(kind, values) of a side spec; a ("wall_from", i0, uwx, uwy, before) spec gives the
+    kind of `before` (its wall segment is set separately)."""
+    if isinstance(spec, (tuple, list)) and spec[0] == "wall_from":
+        return _side(spec[4])
     if isinstance(spec, str):
         spec = (spec,)
     vals = [0.0, 0.0, 0.0]
@@ -220,6 +227,11 @@ class Context:
                 _check(lib().lbfv_set_inflow_eq(self.h, side, v[0], v[1], v[2]), self.h)
             elif kind == 3:
                 _check(lib().lbfv_set_outflow_extrap(self.h, side, int(v[0])), self.h)
+            elif kind == 4:
+                _check(lib().lbfv_set_symmetry(self.h, side), self.h)
+            if isinstance(spec, (tuple, list)) and spec[0] == "wall_from":
+                _check(lib().lbfv_set_wall_from(self.h, side, int(spec[1]), float(spec[2]), float(spec[3])),
+                       self.h)
 
     # ------------------------------------------------------------------ state
     def init_equilibrium(self, rho, ux, uy):
@@ -321,6 +333,8 @@ class Batch:
             cases[i].tau = float(w.tau)
             cases[i].dt = float(w.dt)
             for s, spec in enumerate(w.bcs):
+                if isinstance(spec, (tuple, list)) and spec[0] == "wall_from":
+                    raise ValueError("the batched form takes one boundary kind per side (no wall segments)")
                 kind, v = _side(spec)
                 cases[i].bc_kind[s] = kind
                 for q in range(3):

@@ -91,6 +91,16 @@ def test_state_errors_before_any_device_work():
     assert L.lib().lbfv_step(ctx.h, 4, 1) == L.LBFV_EINVAL
     assert L.lib().lbfv_step(ctx.h, -1, 1) == L.LBFV_EINVAL
     assert L.lib().lbfv_step(ctx.h, L.LBFV_UPWIND, 1) == L.LBFV_ESTATE    # no state yet
+    # symmetry sides and wall segments
+    assert L.lib().lbfv_set_symmetry(ctx.h, 4) == L.LBFV_EINVAL
+    assert L.lib().lbfv_set_wall_from(ctx.h, L.LBFV_WEST, 2, 0.0, 0.0) == L.LBFV_EINVAL   # x-side
+    assert L.lib().lbfv_set_wall_from(ctx.h, L.LBFV_SOUTH, 2, 0.0, 0.0) == L.LBFV_EINVAL  # periodic side
+    L._check(L.lib().lbfv_set_symmetry(ctx.h, L.LBFV_SOUTH), ctx.h)
+    assert L.lib().lbfv_set_wall_from(ctx.h, L.LBFV_SOUTH, 8, 0.0, 0.0) == L.LBFV_EINVAL  # past nx - 1
+    assert L.lib().lbfv_set_wall_from(ctx.h, L.LBFV_SOUTH, -1, 0.0, 0.0) == L.LBFV_EINVAL
+    L._check(L.lib().lbfv_set_wall_from(ctx.h, L.LBFV_SOUTH, 3, 0.01, 0.0), ctx.h)
+    assert L.lib().dugks_step(ctx.h, 1) == L.LBFV_ESTATE      # north left unset by the switch
+    ctx.set_sides(["periodic"] * 4)
     # replacing one side of a periodic axis leaves the other side unset
     L._check(L.lib().lbfv_set_wall(ctx.h, L.LBFV_WEST, 0.0, 0.0), ctx.h)
     assert L.lib().dugks_step(ctx.h, 1) == L.LBFV_ESTATE

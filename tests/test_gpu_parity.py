@@ -129,7 +129,8 @@ def test_edge_sizes(nx, ny):
     for bcs in (["periodic"] * 4,
                 [("wall", 0.0, 0.01), ("wall", 0.0, -0.01), ("wall", 0.02, 0.0), ("wall", -0.01, 0.0)],
                 ["periodic", "periodic", ("wall", 0.0, 0.0), ("inflow", 1.0, 0.02, 0.0)],
-                [("inflow", 1.0, 0.02, 0.0), ("outflow", 0), "periodic", "periodic"]):
+                [("inflow", 1.0, 0.02, 0.0), ("outflow", 0), "periodic", "periodic"],
+                ["symmetry", ("outflow", 0), ("wall_from", 1, 0.01, 0.0, "symmetry"), "symmetry"]):
         w = I.Workload("edge", xf, yf, 0.01, I.cfl_dt(xf, yf, 0.5), bcs, rho, ux, uy)
         ora = oracle_case(w, 1)
         f0 = perturbed_state(ora, w, 7)
@@ -394,8 +395,65 @@ def test_collision_free_interface_values(scheme, oscheme):
     # of one ulp grows to ~2.5e-12 in 1000 steps, so the bar uses the extended oracle
     ext = O.Case(tg.xf, tg.yf, tg.rt, tg.tau, tg.dt, tg.bcs, threads=1, extended=True).run(f0, oscheme, 1000)
     assert_fp64(g, ref, ext, f"sec2.4 scheme={scheme} tg32")
-    g = gpu_run(tg, scheme, 1000, compute=L.LBFV_FP32, storage=L.LBFV_STORE_DEV_FP32)
-    e = u_rel(ora, g, ref)
-    print(f"sec2.4 scheme={scheme} tg32 fp32 u {e:.2e}")
+    # FP32: the central form multiplies rounding by ~2e4 over 1000 steps (see above), so
+    # its FP32 run is compared after 200 steps, where that factor is below 10
+    n32 = 200 if scheme == L.LBFV_CENTRAL else 1000
+    ref32 = ref if n32 == 1000 else ora.run(f0, oscheme, n32)
+    g = gpu_run(tg, scheme, n32, compute=L.LBFV_FP32, storage=L.LBFV_STORE_DEV_FP32)
+    e = u_rel(ora, g, ref32)
+    print(f"sec2.4 scheme={scheme} tg32 fp32 {n32} steps: u {e:.2e}")
     assert e < TOL32_U
 
+
+
+# ------------------------------------------------------------------ symmetry sides, wall segments
+def _symmetry_workloads():
+    xf = I.tanh_faces(130, 1.1, -1.0, 2.0)
+    yf = I.geometric_faces(29, 0.01, 1.0)
+    rho, ux, uy = I.random_state_fields(29, 130, 19, amp_u=0.04, amp_rho=0.02)
+    dt = I.cfl_dt(xf, yf, 0.6)
+    out = []
+    # the split at a strip seam (column 62) and inside a strip (column 40)
+    for i0 in (62, 40):
+        out.append(I.Workload(f"sym{i0}", xf, yf, 0.004, dt,
+                              ["symmetry", ("outflow", 1), ("wall_from", i0, 0.01, 0.0, "symmetry"),
+                               ("inflow", 1.0, 0.05, 0.0)], rho, ux, uy))
+    out.append(I.Workload("sym_box", xf, yf, 0.004, dt,
+                          ["symmetry", "symmetry", "symmetry", ("wall_from", 5, 0.02, 0.0, "symmetry")],
+                          rho, ux, uy))
+    return out
+
+
+@pytest.mark.parametrize("scheme,oscheme", SCHEMES)
+def test_symmetry_sides_and_wall_segments(scheme, oscheme):
+    """Symmetry sides on x and y, and a south / north side that turns into a wall at a
+    strip seam, inside a strip and near the corner: every launch shape gives the same
+    bits and matches the oracle (FP64); FP32 deviation storage within the FP32 bar."""
+    for w in _symmetry_workloads():
+        ora = oracle_case(w)
+        f0 = perturbed_state(ora, w, 23)
+        ref = ora.run(f0, oscheme, 40)
+        outs = []
+        for tile in ((4, 1), (7, 2), (29, 4)):
+            g = gpu_run(w, scheme, 40, f0, tile=tile)
+            print(f"{w.name} scheme={scheme} tile={tile} f {rel(g, ref):.2e}")
+            assert rel(g, ref) < TOL64
+            outs.append(g)
+        for g in outs[1:]:
+            assert np.array_equal(g, outs[0])
+        g = gpu_run(w, scheme, 40, f0, compute=L.LBFV_FP32, storage=L.LBFV_STORE_DEV_FP32)
+        assert u_rel(ora, g, ref) < TOL32_U
+
+
+@pytest.mark.parametrize("dy_min", [0.1, 0.02])
+def test_boundary_layer_paper_mesh_against_oracle(dy_min):
+    """The flat-plate mesh of Sec. 3.3 (120 cells across, symmetry ahead of the plate,
+    wall from the leading edge) from the uniform free stream, 300 steps of each scheme."""
+    w = I.boundary_layer_paper(dy_min)
+    ora = oracle_case(w)
+    f0 = ora.init_equilibrium(w.rho, w.ux, w.uy)
+    for scheme, oscheme in SCHEMES:
+        ref = ora.run(f0, oscheme, 300)
+        g = gpu_run(w, scheme, 300, f0)
+        ext = O.Case(w.xf, w.yf, w.rt, w.tau, w.dt, w.bcs, threads=THREADS, extended=True).run(f0, oscheme, 300)
+        assert_fp64(g, ref, ext, f"bl paper dy={dy_min} scheme={scheme}")
