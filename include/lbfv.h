@@ -167,9 +167,18 @@ int lbfv_residual(lbfv_ctx *ctx, double *r);
  * through, and wavefronts per workgroup (1, 2 or 4).  0 keeps the current value. */
 int lbfv_set_tile(lbfv_ctx *ctx, int32_t rows, int32_t waves_per_block);
 int lbfv_get_tile(const lbfv_ctx *ctx, int32_t *rows, int32_t *waves_per_block);
+/* Time steps per launch of the single-case step: 1, or 2 on a doubly periodic mesh.  With
+ * 2, each wavefront reads its strip of the state once, keeps the intermediate step in
+ * registers and writes the second, so a step moves half the HBM bytes; the result is the
+ * same, bit for bit, as two one-step launches.  The state moves to a 60-column strip
+ * layout (the buffers of lbfv_required_bytes hold either layout).  An odd step count ends
+ * with a one-step launch, and one-step launches are used whenever a side is not periodic.
+ * EINVAL for another value, or for 2 unless all sides are set and periodic. */
+int lbfv_set_time_block(lbfv_ctx *ctx, int32_t steps);
+int lbfv_get_time_block(const lbfv_ctx *ctx, int32_t *steps);
 /* Autotuner: times the candidate shapes for `scheme` on this context (the state is
  * saved and restored), keeps the fastest, and records it in a cache file keyed by
- * (gfx arch, scheme, precision, storage, mesh size class).  cache_path NULL: the
+ * (gfx arch, scheme, precision, storage, time block, mesh size class).  cache_path NULL: the
  * environment variable LBFV_TUNE_CACHE, else no file.  A cached entry is used
  * without timing.  best_ms (nullable) receives the time per step of the choice. */
 int lbfv_autotune(lbfv_ctx *ctx, int scheme, int32_t trial_steps, const char *cache_path,

@@ -9,7 +9,7 @@ namespace lbfv {
 template <typename T>
 __device__ __forceinline__ int64_t cell_offset(const StepParams<T> &P, int64_t k) {
     const int64_t j = k / P.nx, i = k - j * P.nx;
-    return j * P.pitch + col_slot((int)i);
+    return j * P.pitch + col_slot((int)i, P.strip);
 }
 
 // f~ of an equilibrium state (Omega(feq) = 0): x_a = w_a (rho - rho0 + rho P_a(u / c)),
@@ -188,6 +188,22 @@ __global__ __launch_bounds__(RED_BLOCK) void reduce_final_kernel(const double *p
 #pragma unroll
         for (int q = 0; q < RED_N; ++q) v[q] += partial[(int64_t)b * RED_N + q];
     block_sum(v, sh, out);
+}
+
+// Copy a state between the two strip layouts (E: an unsigned type of the stored width).
+template <typename E>
+__global__ void relayout_kernel(const E *src, E *dst, int nx, int ny, int64_t pitch_s, int strip_s,
+                                int64_t pitch_d, int strip_d) {
+    const int64_t n = (int64_t)nx * ny;
+    const int64_t plane_s = pitch_s * ny, plane_d = pitch_d * ny;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = k / nx;
+        const int i = (int)(k - j * nx);
+        const E *p = src + j * pitch_s + col_slot(i, strip_s);
+        E *q = dst + j * pitch_d + col_slot(i, strip_d);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) q[a * plane_d] = p[a * plane_s];
+    }
 }
 
 // Batched form: number of cells holding a non-finite stored value or moment, one block

@@ -57,6 +57,7 @@ struct StepParams {
     T bcv[4][3];            // wall: 6 U_w / c (x, y); inflow: rho, ux / c, uy / c; outflow: order
     int32_t wfrom[4];       // south / north: first cell of a no-slip wall segment (-1: none)
     T wsv[4][2];            // that segment's 6 U_w / c
+    int32_t strip;          // output columns per 64-slot storage block (62, or 60 for two steps per pass)
     T ext[4];               // linear ghost extrapolation factor per side
     T rho0;                 // deviation reference density (0: plain storage)
     T hc;                   // h c, h = dt / 2
@@ -66,10 +67,19 @@ struct StepParams {
 };
 
 // ---------------------------------------------------------------- storage
-constexpr int STRIP = 62;   // output columns per wave
-constexpr int SLOTS = 64;   // storage slots per strip
-__host__ __device__ __forceinline__ int64_t col_slot(int c) { return (int64_t)(c / STRIP) * SLOTS + c % STRIP; }
-__host__ __device__ __forceinline__ int64_t padded_pitch(int nx) { return (int64_t)((nx + STRIP - 1) / STRIP) * SLOTS; }
+// Columns are grouped in strips, each stored in an aligned block of 64 slots (the pad slots
+// are written but never read).  A one-step wave produces 62 columns (lanes 1..62 around a
+// one-column halo), a two-step wave 60 (lanes 2..61 around a two-column halo); the strip
+// width of a state is that of the march that advances it.
+constexpr int STRIP1 = 62;
+constexpr int STRIP2 = 60;
+constexpr int SLOTS = 64;
+__host__ __device__ __forceinline__ int64_t col_slot(int c, int strip) {
+    return (int64_t)(c / strip) * SLOTS + c % strip;
+}
+__host__ __device__ __forceinline__ int64_t padded_pitch(int nx, int strip) {
+    return (int64_t)((nx + strip - 1) / strip) * SLOTS;
+}
 
 template <typename S> struct Storage;
 // (direction indices are compile-time constants once the 9-loops are unrolled)
@@ -231,8 +241,10 @@ __device__ __forceinline__ T dfeq(int A, const Mom<T> &m) {
 // ---------------------------------------------------------------- the strip march
 // BND = false compiles out every ghost-cell and bounce-back path; it is used when both
 // axes are periodic (rows and columns then wrap and no wall face exists), which keeps
-// the register budget of the interior loop small.
-template <typename T, typename S, int SCHEME, bool BND>
+// the register budget of the interior loop small.  HALO = 1: one step per pass, lane l
+// holds column x0-1+l; HALO = 2 (periodic meshes only): two steps per pass, lane l holds
+// column x0-2+l and the intermediate step stays in registers.
+template <typename T, typename S, int SCHEME, bool BND, int HALO = 1>
 struct March {
     const StepParams<T> &P;
     const S *__restrict__ src;
@@ -252,7 +264,7 @@ struct March {
 
     __device__ March(const StepParams<T> &p, const S *s, S *d, int x0) : P(p), src(s), dst(d) {
         lane = threadIdx.x & 63;
-        col = x0 - 1 + lane;
+        col = x0 - HALO + lane;
         const int nx = P.nx;
         per_x = !BND || P.bc[SIDE_W] == BC_PERIODIC;
         per_y = !BND || P.bc[SIDE_S] == BC_PERIODIC;
@@ -260,18 +272,28 @@ struct March {
         else ccol = col < 0 ? 0 : (col >= nx ? nx - 1 : col);
         if (ccol >= nx) ccol = nx - 1;   // garbage lanes past a short periodic row
         if (ccol < 0) ccol = 0;
-        lslot = col_slot(ccol);
-        // lanes 1..62 own slots 0..61 of this strip's block, lanes 0 and 63 the two pad
-        // slots: the wave writes its 64-slot block whole (pad values are never read)
-        sslot = (int64_t)(x0 / STRIP) * SLOTS + (lane == 0 ? STRIP : (lane == 63 ? STRIP + 1 : lane - 1));
+        lslot = col_slot(ccol, P.strip);
+        // the output lanes HALO..HALO+strip-1 own slots 0..strip-1 of this strip's block and
+        // the remaining lanes the pad slots: the wave writes its 64-slot block whole (pad
+        // values are never read)
+        sslot = (int64_t)(x0 / P.strip) * SLOTS + ((lane - HALO) & (SLOTS - 1));
         ghostW = BND && !per_x && x0 == 0;
         segS = BND && P.wfrom[SIDE_S] >= 0 && col >= P.wfrom[SIDE_S];
         segN = BND && P.wfrom[SIDE_N] >= 0 && col >= P.wfrom[SIDE_N];
         laneE = nx - x0 + 1;
         ghostE = BND && !per_x && laneE <= 63;
         const T *lam = P.xm, *id = P.xm + (nx + 1), *is = P.xm + 2 * (nx + 1), *cd = is + nx;
+        // HALO = 1: a halo lane only needs the face it shares with the strip; HALO = 2 (a
+        // periodic axis): every lane advances its own (wrapped) column once, so it takes
+        // that column's metrics (the metric arrays hold the seam face at index 0 and nx
+        // with identical values)
         int fE = min(max(col + 1, 0), nx), fW = min(max(col, 0), nx);
         int ci = min(max(col, 0), nx - 1);
+        if (HALO == 2) {
+            fW = ccol;
+            fE = ccol + 1;
+            ci = ccol;
+        }
         const T lE = lam[fE], iE = id[fE], lW = lam[fW], iW = id[fW];
         // face value phi_L + c (phi_R - phi_L) with c = lam - e_x h c id; both lanes that
         // share a face compute the same c from the same metric entries
@@ -310,6 +332,9 @@ struct March {
         for (int a = 0; a < 9; ++a) {
             x[a] = Storage<S>::load(raw[a], a);
         }
+        cell_t(x, phi, psi);
+    }
+    __device__ __forceinline__ void cell_t(const T (&x)[9], T (&phi)[9], T (&psi)[9]) const {
         const Mom<T> m = moments(x, P.rho0);
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
@@ -442,6 +467,65 @@ struct March {
         }
     }
 
+    // ---- the update of one row (rows k-1, k, k+1 of phi in Pm, P0, Pp; psi of row k in
+    // S0; fS = y-face values south of row k, replaced by those north of it).  r is the row
+    // index in [0, ny) (the two-step march passes wrapped rows of a periodic mesh).
+    __device__ __forceinline__ void advance(int r, const T (&Pm)[9], const T (&P0)[9], const T (&Pp)[9],
+                                            const T (&S0)[9], T (&fS)[9], T (&v)[9]) const {
+        const int ny = P.ny;
+        // x-faces at row r
+        T sy[9];
+        const T isy = ldc(P.ym, 2 * (ny + 1) + r);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            if (EY[a] != 0) sy[a] = (Pp[a] - Pm[a]) * isy;
+            else sy[a] = (T)0;
+        }
+        T fW[9];
+        xface(P0, sy, fW);
+        if (ghostW && P.bc[SIDE_W] == BC_WALL)
+            bounce<-1, 0>(fW, P.bcv[SIDE_W][0], P.bcv[SIDE_W][1], lane == 1);
+        if (ghostW && P.bc[SIDE_W] == BC_SYMMETRY) specular<-1, 0>(fW, lane == 1);
+        if (ghostE && P.bc[SIDE_E] == BC_WALL)
+            bounce<1, 0>(fW, P.bcv[SIDE_E][0], P.bcv[SIDE_E][1], lane == laneE);
+        if (ghostE && P.bc[SIDE_E] == BC_SYMMETRY) specular<1, 0>(fW, lane == laneE);
+        face_mix<0>(fW);
+
+        // y-face north of row r
+        T fN[9];
+        yface(r + 1, P0, Pp, fN);
+        if (BND && r + 1 == ny) {
+            if (P.bc[SIDE_N] == BC_WALL) bounce<0, 1>(fN, P.bcv[SIDE_N][0], P.bcv[SIDE_N][1], !segN);
+            if (P.bc[SIDE_N] == BC_SYMMETRY) specular<0, 1>(fN, !segN);
+            if (P.wfrom[SIDE_N] >= 0) bounce<0, 1>(fN, P.wsv[SIDE_N][0], P.wsv[SIDE_N][1], segN);
+        }
+        face_mix<1>(fN);
+
+        // flux divergence and update, Eq. eq_update with the sign of Eq. bkg_fv (reading R1)
+        const T cdy = ldc(P.ym, 3 * ny + 2 + r);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            T u = (SCHEME == SCHEME_DUGKS) ? S0[a] : P0[a];
+            if (EX[a] != 0) {
+                const T fE = shl1(fW[a]);
+                u = fma(EX[a] > 0 ? -cdx : cdx, fE - fW[a], u);
+            }
+            if (EY[a] != 0) u = fma(EY[a] > 0 ? -cdy : cdy, fN[a] - fS[a], u);
+            v[a] = u;
+        }
+#pragma unroll
+        for (int a = 0; a < 9; ++a) fS[a] = fN[a];
+    }
+
+    __device__ __forceinline__ void store_row(int r, const T (&v)[9]) const {
+        S *out = dst + (int64_t)r * P.pitch + sslot;
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            // streaming store: the new state is not read again within this step
+            __builtin_nontemporal_store(Storage<S>::store(v[a], a), out + a * P.plane);
+        }
+    }
+
     // ---- one output row k.  Pm, P0, Pp = phi rows k-1, k, k+1; S0 = psi row k;
     // fS = y-face values south of row k; Rnext = stored values of row k+2 (loaded by the
     // previous row).  Produces the row-k update and the y-face values north of row k
@@ -459,50 +543,9 @@ struct March {
         const bool load_real = k + 2 < j1 && (!BND || (k + 3 < ny) || per_y);
         load(load_real ? k + 3 : k, Rnew);
 
-        // x-faces at row k
-        T sy[9];
-        const T isy = ldc(P.ym, 2 * (ny + 1) + k);
-#pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            if (EY[a] != 0) sy[a] = (Pp[a] - Pm[a]) * isy;
-            else sy[a] = (T)0;
-        }
-        T fW[9];
-        xface(P0, sy, fW);
-        if (ghostW && P.bc[SIDE_W] == BC_WALL)
-            bounce<-1, 0>(fW, P.bcv[SIDE_W][0], P.bcv[SIDE_W][1], lane == 1);
-        if (ghostW && P.bc[SIDE_W] == BC_SYMMETRY) specular<-1, 0>(fW, lane == 1);
-        if (ghostE && P.bc[SIDE_E] == BC_WALL)
-            bounce<1, 0>(fW, P.bcv[SIDE_E][0], P.bcv[SIDE_E][1], lane == laneE);
-        if (ghostE && P.bc[SIDE_E] == BC_SYMMETRY) specular<1, 0>(fW, lane == laneE);
-        face_mix<0>(fW);
-
-        // y-face north of row k
-        T fN[9];
-        yface(k + 1, P0, Pp, fN);
-        if (BND && k + 1 == ny) {
-            if (P.bc[SIDE_N] == BC_WALL) bounce<0, 1>(fN, P.bcv[SIDE_N][0], P.bcv[SIDE_N][1], !segN);
-            if (P.bc[SIDE_N] == BC_SYMMETRY) specular<0, 1>(fN, !segN);
-            if (P.wfrom[SIDE_N] >= 0) bounce<0, 1>(fN, P.wsv[SIDE_N][0], P.wsv[SIDE_N][1], segN);
-        }
-        face_mix<1>(fN);
-
-        // flux divergence and update, Eq. eq_update with the sign of Eq. bkg_fv (reading R1)
-        const T cdy = ldc(P.ym, 3 * ny + 2 + k);
-        S *out = dst + (int64_t)k * P.pitch + sslot;
-#pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            T v = (SCHEME == SCHEME_DUGKS) ? S0[a] : P0[a];
-            if (EX[a] != 0) {
-                const T fE = shl1(fW[a]);
-                v = fma(EX[a] > 0 ? -cdx : cdx, fE - fW[a], v);
-            }
-            if (EY[a] != 0) v = fma(EY[a] > 0 ? -cdy : cdy, fN[a] - fS[a], v);
-            // streaming store: the new state is not read again within this step
-            __builtin_nontemporal_store(Storage<S>::store(v, a), out + a * P.plane);
-        }
-#pragma unroll
-        for (int a = 0; a < 9; ++a) fS[a] = fN[a];
+        T v[9];
+        advance(k, Pm, P0, Pp, S0, fS, v);
+        store_row(k, v);
 
         // next row (k + 2) into the free slot
         if (need_next) {
@@ -513,6 +556,43 @@ struct March {
                 ghost_y(SIDE_N, Pp, P0, Pm);
             }
         }
+    }
+
+    // ---- two steps per pass (HALO = 2, periodic mesh).  Level 0 is the stored state,
+    // level 1 the state after one step (registers only), level 2 after two (stored).  The
+    // call for row k advances level 0 at row k (rows j0-1 .. j1 of a block), turns it into
+    // phi / psi of level 1 in Qk / Uk, and advances level 1 at row k-1 (rows j0 .. j1-1),
+    // which is stored.  Level-0 roles are those of body(); Qm2, Qm1 = level-1 phi rows
+    // k-2, k-1; Um1 = level-1 psi row k-1; gS = level-1 y-face values south of row k-1.
+    // Each face is evaluated with the metrics the one-step march uses for it, so the two
+    // passes give the same bits as two one-step launches.
+    __device__ __forceinline__ void body2(int k, int j0, int j1, T (&Pm)[9], T (&P0)[9], T (&Pp)[9],
+                                          T (&Sm)[9], T (&S0)[9], T (&fS)[9], S (&Rnew)[9], S (&Rnext)[9],
+                                          T (&Qm2)[9], T (&Qm1)[9], T (&Qk)[9], T (&Um1)[9], T (&Uk)[9],
+                                          T (&gS)[9]) {
+        const bool need_next = k < j1;        // the call for row k+1 needs level-0 phi of row k+2
+        const bool load_real = k + 1 < j1;    // ... and the call after it row k+3
+        load(load_real ? k + 3 : k, Rnew);
+
+        const int r = row_index(k);
+        if (r == 0 && k != j0 - 1) {
+            // row 0 entered across the periodic seam: its south face is face 0, as in a
+            // one-step pass (which always starts a row block there)
+            yface(0, Pm, P0, fS);
+            face_mix<1>(fS);
+        }
+        T v[9];
+        advance(r, Pm, P0, Pp, S0, fS, v);     // level 1 of row k
+        cell_t(v, Qk, Uk);
+        if (k == j0) {
+            yface(j0, Qm1, Qk, gS);           // level-1 face south of row j0
+            face_mix<1>(gS);
+        } else if (k > j0) {
+            T w[9];
+            advance(k - 1, Qm2, Qm1, Qk, Um1, gS, w);   // level 2 of row k-1
+            store_row(k - 1, w);
+        }
+        if (need_next) cell(Rnext, Pm, Sm);
     }
 
     __device__ __forceinline__ void run(int j0, int j1) {
@@ -561,6 +641,32 @@ struct March {
             body(k + 2, j1, PC, PA, PB, SC, SA, fS, R0, R2);
         }
     }
+
+    // two steps per pass over rows [j0, j1) of a periodic mesh (HALO = 2)
+    __device__ __forceinline__ void run2(int j0, int j1) {
+        T PA[9], PB[9], PC[9], SA[9], SB[9], SC[9], fS[9];
+        T QA[9], QB[9], QC[9], UA[9], UB[9], UC[9], gS[9];
+        S R0[9], R1[9], R2[9], R3[9];
+        // prologue: level-0 phi of rows j0-2, j0-1, j0 (PA, PB, PC) and psi; row j0+1 is
+        // the first call's next row (R0); the first call prefetches row j0+2
+        load(j0 - 2, R3);
+        load(j0 - 1, R1);
+        load(j0, R2);
+        load(j0 + 1, R0);
+        cell(R3, PA, SA);
+        cell(R1, PB, SB);
+        cell(R2, PC, SC);
+        yface(row_index(j0 - 1), PA, PB, fS);
+        face_mix<1>(fS);
+
+        for (int k = j0 - 1; k <= j1; k += 3) {
+            body2(k, j0, j1, PA, PB, PC, SA, SB, fS, R1, R0, QB, QC, QA, UC, UA, gS);
+            if (k + 1 > j1) break;
+            body2(k + 1, j0, j1, PB, PC, PA, SB, SC, fS, R2, R1, QC, QA, QB, UA, UB, gS);
+            if (k + 2 > j1) break;
+            body2(k + 2, j0, j1, PC, PA, PB, SC, SA, fS, R0, R2, QA, QB, QC, UB, UC, gS);
+        }
+    }
 };
 
 // Logical block index such that consecutive logical blocks run on one XCD: the
@@ -588,8 +694,26 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams<T> P, int parity, 
     const int j0 = sy * rows, j1 = min(P.ny, j0 + rows);
     const S *src = (const S *)P.buf[parity];
     S *dst = (S *)P.buf[parity ^ 1];
-    March<T, S, SCHEME, BND> m(P, src, dst, 62 * sx);
+    March<T, S, SCHEME, BND> m(P, src, dst, P.strip * sx);
     m.run(j0, j1);
+}
+
+// Two time steps per launch on a doubly periodic mesh (state in the 60-column strip
+// layout): each wave reads its strip once, keeps the intermediate step in registers and
+// stores the second; a launch reads buf[parity] and writes buf[1-parity].
+template <typename T, typename S, int SCHEME>
+__global__ __launch_bounds__(256) void step2_kernel(StepParams<T> P, int parity, int rows, int nstrips,
+                                                    int nwork) {
+    const int rb = xcd_block();
+    const int wpb = blockDim.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(rb * wpb + (int)(threadIdx.x >> 6));
+    if (w >= nwork) return;
+    const int sx = w % nstrips, sy = w / nstrips;
+    const int j0 = sy * rows, j1 = min(P.ny, j0 + rows);
+    const S *src = (const S *)P.buf[parity];
+    S *dst = (S *)P.buf[parity ^ 1];
+    March<T, S, SCHEME, false, 2> m(P, src, dst, P.strip * sx);
+    m.run2(j0, j1);
 }
 
 }  // namespace lbfv

@@ -6,6 +6,7 @@
 #include "batch_kernels.hpp"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -32,6 +33,8 @@ struct HostCase {
     double wsv[4][2] = {};             // the segment's wall velocity
     int variant = V_F64;
     double rho0 = 0.0;        // 0 for native storage
+    int strip = STRIP1;       // output columns per 64-slot block of the current state
+    int tblock = 1;           // time steps per launch of the single-case step (1 or 2)
     int64_t pitch = 0, plane = 0;
     size_t esize = 8;
     void *buf[2] = {nullptr, nullptr};
@@ -41,7 +44,13 @@ struct HostCase {
     double *d_dx = nullptr, *d_dy = nullptr; // cell sizes (FP64) for volumes
     bool metrics_dirty = true;
 
-    size_t buffer_bytes() const { return (size_t)plane * 9 * esize; }
+    // buffers fit the state in either strip layout
+    size_t buffer_bytes() const { return (size_t)padded_pitch(nx, STRIP2) * ny * 9 * esize; }
+    void set_strip(int w) {
+        strip = w;
+        pitch = padded_pitch(nx, w);
+        plane = pitch * ny;
+    }
     bool sides_set() const { return bc[0] >= 0 && bc[1] >= 0 && bc[2] >= 0 && bc[3] >= 0; }
     bool periodic_x() const { return bc[SIDE_W] == BC_PERIODIC; }
     bool periodic_y() const { return bc[SIDE_S] == BC_PERIODIC; }
@@ -65,9 +74,9 @@ struct lbfv_ctx {
     bool unstable = false;
     int64_t steps = 0, steps_at_check = 0;
     int rows = 0, wpb = 4;
-    // graphs of `gsteps` launches, per scheme and starting buffer
+    // graphs of `gsteps` launches, per scheme (+4 for two steps per launch) and starting buffer
     int gsteps = 32;
-    hipGraphExec_t gexec[4][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+    hipGraphExec_t gexec[8][2] = {};
     // reductions
     double *d_partial = nullptr, *d_out = nullptr, *h_out = nullptr, *d_uprev = nullptr;
     int red_blocks = 0;
@@ -132,6 +141,12 @@ void axis_metrics(const std::vector<double> &f, bool periodic, double dt, double
         m[g] = (f[g] - X(g - 1)) / d;
         m[n + 1 + g] = 1.0 / d;
     }
+    if (periodic) {
+        // faces 0 and n are the same face of a periodic axis: one set of values, so
+        // that every march evaluates it identically whichever end it reaches it from
+        m[n] = m[0];
+        m[n + 1 + n] = m[n + 1];
+    }
     for (int i = 0; i < n; ++i) {
         m[2 * n + 2 + i] = 1.0 / (X(i + 1) - X(i - 1));
         m[3 * n + 2 + i] = dt * c / sizes[i];
@@ -156,6 +171,7 @@ StepParams<T> make_params(const HostCase &h, double ext[4], int scheme = SCHEME_
     P.ny = h.ny;
     P.pitch = h.pitch;
     P.plane = h.plane;
+    P.strip = h.strip;
     P.xm = (const T *)h.d_xm;
     P.ym = (const T *)h.d_ym;
     for (int s = 0; s < 4; ++s) {
@@ -247,7 +263,7 @@ StepShape step_shape(const HostCase &h, int rows, int wpb) {
     StepShape s;
     s.rows = rows;
     s.wpb = wpb;
-    s.nstrips = (h.nx + 61) / 62;
+    s.nstrips = (h.nx + h.strip - 1) / h.strip;
     s.nwork = s.nstrips * ((h.ny + rows - 1) / rows);
     s.nblocks = (s.nwork + wpb - 1) / wpb;
     return s;
@@ -261,6 +277,18 @@ void *step_fn_b(int scheme) {
 template <typename T, typename S>
 void *step_fn(int scheme, bool bnd) {
     return bnd ? step_fn_b<T, S, true>(scheme) : step_fn_b<T, S, false>(scheme);
+}
+template <typename T, typename S>
+void *step2_fn(int scheme) {
+    return scheme == SCHEME_BKG ? (void *)step2_kernel<T, S, SCHEME_BKG> : (void *)step2_kernel<T, S, SCHEME_DUGKS>;
+}
+void *step2_fn_variant(int variant, int scheme) {
+    switch (variant) {
+    case V_F64: return step2_fn<double, double>(scheme);
+    case V_F32: return step2_fn<float, float>(scheme);
+    case V_BF16: return step2_fn<float, __bf16>(scheme);
+    default: return step2_fn<float, _Float16>(scheme);
+    }
 }
 // bnd: some side is not periodic (ghost cells / walls present)
 void *step_fn_variant(int variant, int scheme, bool bnd) {
@@ -335,7 +363,7 @@ int resident_waves(void *fn, int wpb) {
 std::vector<int> balanced_rows(const HostCase &h, int slots) {
     std::vector<int> out;
     if (slots <= 0) return out;
-    const int nstrips = (h.nx + 61) / 62;
+    const int nstrips = (h.nx + h.strip - 1) / h.strip;
     for (int k = 1; k <= 4; ++k) {
         const int blocks = (k * slots) / nstrips;   // row blocks per strip
         if (blocks < 1) continue;
@@ -436,8 +464,7 @@ void init_host_case(HostCase &h, const lbfv_mesh *mesh, const lbfv_velset *vel, 
     else h.variant = V_F32;
     h.rho0 = storage == LBFV_STORE_NATIVE ? 0.0 : rho0;
     h.esize = h.variant == V_F64 ? 8 : (h.variant == V_F32 ? 4 : 2);
-    h.pitch = padded_pitch(h.nx);   // strip-padded rows (see kernels.hpp)
-    h.plane = h.pitch * h.ny;
+    h.set_strip(STRIP1);   // strip-padded rows (see kernels.hpp)
 }
 
 int set_side(HostCase &h, int side, int kind, double a, double b, double c) {
@@ -503,17 +530,22 @@ void current_ext(const HostCase &h, double ext[4]) {
     axis_metrics(h.yf, h.periodic_y(), h.dt, h.c, m, ext[SIDE_S], ext[SIDE_N], s);
 }
 
-int launch_one(lbfv_ctx *c, int scheme, int parity, const double ext[4]) {
+// the step kernel of a launch: two steps per launch (periodic meshes in the 60-column
+// layout) or one
+void *launch_fn(const HostCase &h, int scheme, bool two) {
+    return two ? step2_fn_variant(h.variant, scheme) : step_fn_variant(h.variant, scheme, has_boundary(h));
+}
+
+int launch_one(lbfv_ctx *c, int scheme, int parity, const double ext[4], bool two = false) {
     HostCase &h = c->hc;
     StepShape sh = step_shape(h, c->rows, c->wpb);
     StepArgs a;
     fill_args(h, ext, sh, parity, scheme, a);
-    HIPCHK(hipLaunchKernel(step_fn_variant(h.variant, scheme, has_boundary(h)), dim3(sh.nblocks), dim3(64 * sh.wpb), a.args, 0,
-                           c->stream));
+    HIPCHK(hipLaunchKernel(launch_fn(h, scheme, two), dim3(sh.nblocks), dim3(64 * sh.wpb), a.args, 0, c->stream));
     return LBFV_OK;
 }
 
-int build_graph(lbfv_ctx *c, int scheme, int parity0, const double ext[4]) {
+int build_graph(lbfv_ctx *c, int scheme, int parity0, const double ext[4], bool two = false) {
     HostCase &h = c->hc;
     StepShape sh = step_shape(h, c->rows, c->wpb);
     hipGraph_t g;
@@ -524,7 +556,7 @@ int build_graph(lbfv_ctx *c, int scheme, int parity0, const double ext[4]) {
         fill_args(h, ext, sh, (parity0 + s) & 1, scheme, a);
         hipKernelNodeParams kp;
         memset(&kp, 0, sizeof(kp));
-        kp.func = step_fn_variant(h.variant, scheme, has_boundary(h));
+        kp.func = launch_fn(h, scheme, two);
         kp.gridDim = dim3(sh.nblocks);
         kp.blockDim = dim3(64 * sh.wpb);
         kp.sharedMemBytes = 0;
@@ -538,7 +570,7 @@ int build_graph(lbfv_ctx *c, int scheme, int parity0, const double ext[4]) {
         }
         prev = node;
     }
-    hipError_t e = hipGraphInstantiate(&c->gexec[scheme][parity0], g, nullptr, nullptr, 0);
+    hipError_t e = hipGraphInstantiate(&c->gexec[scheme + (two ? 4 : 0)][parity0], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return c->fail(LBFV_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     return LBFV_OK;
@@ -621,6 +653,9 @@ int do_steps(lbfv_ctx *c, int scheme, int32_t n) {
     if (st) return st;
     current_ext(h, ext);
     if (c->rows <= 0) c->rows = default_rows(h, scheme, c->wpb);
+    // two steps per launch while both axes are periodic; an odd step is a one-step launch
+    const bool two = h.tblock == 2 && !has_boundary(h);
+    const int per = two ? 2 : 1;
     while (n > 0) {
         int seg = n;
         if (c->check_every > 0) {
@@ -628,17 +663,22 @@ int do_steps(lbfv_ctx *c, int scheme, int32_t n) {
             seg = (int)std::min<int64_t>(seg, std::max<int64_t>(to_check, 1));
         }
         int left = seg;
-        while (left >= c->gsteps) {
-            hipGraphExec_t &g = c->gexec[scheme][h.cur];
+        while (left >= per * c->gsteps) {
+            hipGraphExec_t &g = c->gexec[scheme + (two ? 4 : 0)][h.cur];
             if (!g) {
-                st = build_graph(c, scheme, h.cur, ext);
+                st = build_graph(c, scheme, h.cur, ext, two);
                 if (st) return st;
             }
             HIPCHK(hipGraphLaunch(g, c->stream));
             h.cur ^= (c->gsteps & 1);
-            left -= c->gsteps;
+            left -= per * c->gsteps;
         }
-        for (; left > 0; --left) {
+        for (; left >= per; left -= per) {
+            st = launch_one(c, scheme, h.cur, ext, two);
+            if (st) return st;
+            h.cur ^= 1;
+        }
+        if (left > 0) {
             st = launch_one(c, scheme, h.cur, ext);
             if (st) return st;
             h.cur ^= 1;
@@ -1015,6 +1055,47 @@ int lbfv_residual(lbfv_ctx *c, double *r) {
     return LBFV_OK;
 }
 
+int lbfv_set_time_block(lbfv_ctx *c, int32_t steps) {
+    if (!c) return LBFV_EINVAL;
+    HostCase &h = c->hc;
+    if (steps != 1 && steps != 2) return c->fail(LBFV_EINVAL, "lbfv_set_time_block: steps must be 1 or 2");
+    if (steps == 2 && !(h.sides_set() && h.periodic_x() && h.periodic_y()))
+        return c->fail(LBFV_EINVAL, "lbfv_set_time_block: two steps per launch need both axes periodic");
+    const int w = steps == 2 ? STRIP2 : STRIP1;
+    if (w != h.strip) {
+        if (c->has_state) {
+            // move the current state into the other buffer in the new layout
+            int st = poll_check(c, true);
+            if (st) return st;
+            const int64_t n = (int64_t)h.nx * h.ny;
+            const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+            const int64_t pitch_d = padded_pitch(h.nx, w);
+            void *src = h.buf[h.cur], *dst = h.buf[h.cur ^ 1];
+            if (h.esize == 8)
+                hipLaunchKernelGGL(relayout_kernel<uint64_t>, dim3(blocks), dim3(256), 0, c->stream,
+                                   (const uint64_t *)src, (uint64_t *)dst, h.nx, h.ny, h.pitch, h.strip, pitch_d, w);
+            else if (h.esize == 4)
+                hipLaunchKernelGGL(relayout_kernel<uint32_t>, dim3(blocks), dim3(256), 0, c->stream,
+                                   (const uint32_t *)src, (uint32_t *)dst, h.nx, h.ny, h.pitch, h.strip, pitch_d, w);
+            else
+                hipLaunchKernelGGL(relayout_kernel<uint16_t>, dim3(blocks), dim3(256), 0, c->stream,
+                                   (const uint16_t *)src, (uint16_t *)dst, h.nx, h.ny, h.pitch, h.strip, pitch_d, w);
+            HIPCHK(hipGetLastError());
+            h.cur ^= 1;
+        }
+        h.set_strip(w);
+        drop_graphs(c);
+    }
+    h.tblock = steps;
+    return LBFV_OK;
+}
+
+int lbfv_get_time_block(const lbfv_ctx *c, int32_t *steps) {
+    if (!c || !steps) return LBFV_EINVAL;
+    *steps = c->hc.tblock;
+    return LBFV_OK;
+}
+
 int lbfv_set_tile(lbfv_ctx *c, int32_t rows, int32_t wpb) {
     if (!c) return LBFV_EINVAL;
     if (rows < 0 || (wpb != 0 && wpb != 1 && wpb != 2 && wpb != 4))
@@ -1054,12 +1135,12 @@ int size_class(int n) {
 std::string tune_key(const HostCase &h, int scheme) {
     std::ostringstream s;
     static const char *names[4] = {"dugks", "bkg", "central", "upwind"};
-    s << arch_name() << " " << names[scheme] << " v" << h.variant << " x"
+    s << arch_name() << " " << names[scheme] << " v" << h.variant << (has_boundary(h) ? " b" : " p") << " x"
       << size_class(h.nx) << " y" << size_class(h.ny);
     return s.str();
 }
 
-bool cache_lookup(const char *path, const std::string &key, int &rows, int &wpb, double &ms) {
+bool cache_lookup(const char *path, const std::string &key, int &rows, int &wpb, double &ms, int &tb) {
     if (!path) return false;
     std::ifstream in(path);
     std::string line;
@@ -1067,12 +1148,14 @@ bool cache_lookup(const char *path, const std::string &key, int &rows, int &wpb,
     while (std::getline(in, line)) {
         if (line.compare(0, key.size(), key) == 0 && line.size() > key.size() && line[key.size()] == '|') {
             std::istringstream t(line.substr(key.size() + 1));
-            int r, w;
+            int r, w, k = 1;
             double m;
             if (t >> r >> w >> m) {
+                if (!(t >> k) || (k != 1 && k != 2)) k = 1;
                 rows = r;
                 wpb = w;
                 ms = m;
+                tb = k;
                 found = true;   // last entry wins
             }
         }
@@ -1080,10 +1163,10 @@ bool cache_lookup(const char *path, const std::string &key, int &rows, int &wpb,
     return found;
 }
 
-void cache_store(const char *path, const std::string &key, int rows, int wpb, double ms) {
+void cache_store(const char *path, const std::string &key, int rows, int wpb, double ms, int tb) {
     if (!path) return;
     std::ofstream out(path, std::ios::app);
-    out << key << "|" << rows << " " << wpb << " " << ms << "\n";
+    out << key << "|" << rows << " " << wpb << " " << ms << " " << tb << "\n";
 }
 
 }  // namespace
@@ -1098,22 +1181,25 @@ extern "C" int lbfv_autotune(lbfv_ctx *c, int scheme, int32_t trial_steps, const
     const char *path = cache_path ? cache_path : getenv("LBFV_TUNE_CACHE");
     HostCase &h = c->hc;
     const std::string key = tune_key(h, scheme);
-    int rows, wpb;
+    int rows, wpb, tb;
     double ms;
-    if (cache_lookup(path, key, rows, wpb, ms)) {
+    if (cache_lookup(path, key, rows, wpb, ms, tb)) {
+        if (tb == 2 && has_boundary(h)) tb = 1;
+        int st = lbfv_set_time_block(c, tb);
+        if (st) return st;
         c->rows = std::min(rows, h.ny);
         c->wpb = wpb;
         drop_graphs(c);
         if (best_ms) *best_ms = ms;
         return LBFV_OK;
     }
-    // save the state; trials step it
+    // save the state; trials step it (and may move it between strip layouts)
     void *save = nullptr;
     if (hipMalloc(&save, h.buffer_bytes()) != hipSuccess) {
         (void)hipGetLastError();
         return c->fail(LBFV_ENOMEM, "autotune: cannot allocate the save buffer");
     }
-    const int saved_cur = h.cur;
+    const int saved_cur = h.cur, saved_strip = h.strip, saved_tb = h.tblock;
     const int64_t saved_steps = c->steps, saved_at = c->steps_at_check;
     const int saved_check = c->check_every;
     HIPCHK(hipMemcpyAsync(save, h.buf[h.cur], h.buffer_bytes(), hipMemcpyDeviceToDevice, c->stream));
@@ -1121,22 +1207,28 @@ extern "C" int lbfv_autotune(lbfv_ctx *c, int scheme, int32_t trial_steps, const
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     c->check_every = 0;
-    int best_r = 0, best_w = 0;
+    int best_r = 0, best_w = 0, best_t = 1;
     double best = INFINITY;
-    const int w_opts[] = {1, 2, 4};
     int st = LBFV_OK;
-    std::vector<std::pair<int, int>> cands;
-    for (int w : w_opts) {
-        for (int r : {4, 8, 16, 32, 64, 128, 256})
-            if (r <= h.ny || r == 4) cands.push_back({std::min(r, h.ny), w});
-        for (int r : balanced_rows(h, resident_waves(step_fn_variant(h.variant, scheme, has_boundary(h)), w)))
-            cands.push_back({r, w});
+    // candidate shapes: (time block, rows, waves per block); two steps per launch only on a
+    // doubly periodic mesh
+    std::vector<std::array<int, 3>> cands;
+    for (int t : {1, 2}) {
+        if (t == 2 && has_boundary(h)) continue;
+        for (int w : {1, 2, 4}) {
+            for (int r : {4, 8, 16, 32, 64, 128, 256})
+                if (r <= h.ny || r == 4) cands.push_back({t, std::min(r, h.ny), w});
+            if (t == 1)
+                for (int r : balanced_rows(h, resident_waves(step_fn_variant(h.variant, scheme, has_boundary(h)), w)))
+                    cands.push_back({t, r, w});
+        }
     }
     std::sort(cands.begin(), cands.end());
     cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
-    for (const auto &rw : cands) {
-        c->rows = rw.first;
-        c->wpb = rw.second;
+    for (const auto &cand : cands) {
+        if ((st = lbfv_set_time_block(c, cand[0]))) break;
+        c->rows = cand[1];
+        c->wpb = cand[2];
         drop_graphs(c);
         if ((st = do_steps(c, scheme, 2))) break;   // warm-up
         hipEventRecord(e0, c->stream);
@@ -1148,11 +1240,14 @@ extern "C" int lbfv_autotune(lbfv_ctx *c, int scheme, int32_t trial_steps, const
         const double per = t / trial_steps;
         if (per < best) {
             best = per;
-            best_r = rw.first;
-            best_w = rw.second;
+            best_t = cand[0];
+            best_r = cand[1];
+            best_w = cand[2];
         }
     }
-    // restore
+    // restore the saved state in its own layout, then move it to the chosen one
+    h.set_strip(saved_strip);
+    h.tblock = saved_tb;
     h.cur = saved_cur;
     hipMemcpyAsync(h.buf[h.cur], save, h.buffer_bytes(), hipMemcpyDeviceToDevice, c->stream);
     hipStreamSynchronize(c->stream);
@@ -1162,11 +1257,13 @@ extern "C" int lbfv_autotune(lbfv_ctx *c, int scheme, int32_t trial_steps, const
     c->steps = saved_steps;
     c->steps_at_check = saved_at;
     c->check_every = saved_check;
+    drop_graphs(c);
     if (st) return st;
+    if ((st = lbfv_set_time_block(c, best_t))) return st;
     c->rows = best_r;
     c->wpb = best_w;
     drop_graphs(c);
-    cache_store(path, key, best_r, best_w, best);
+    cache_store(path, key, best_r, best_w, best, best_t);
     if (best_ms) *best_ms = best;
     return LBFV_OK;
 }
@@ -1212,7 +1309,7 @@ int batch_build_items(lbfv_batch *b) {
         const HostCase &h = b->cases[ci];
         const int rows = std::min(b->rows, h.ny);
         for (int j0 = 0; j0 < h.ny; j0 += rows)
-            for (int x0 = 0; x0 < h.nx; x0 += 62) items.push_back({ci, x0, j0, std::min(h.ny, j0 + rows)});
+            for (int x0 = 0; x0 < h.nx; x0 += h.strip) items.push_back({ci, x0, j0, std::min(h.ny, j0 + rows)});
     }
     if (b->d_items) (void)hipFree(b->d_items);
     b->d_items = nullptr;

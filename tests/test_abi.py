@@ -87,6 +87,9 @@ def test_state_errors_before_any_device_work():
     assert L.lib().lbfv_set_inflow_eq(ctx.h, 0, -1.0, 0.0, 0.0) == L.LBFV_EINVAL
     assert L.lib().lbfv_set_periodic(ctx.h, 5) == L.LBFV_EINVAL
     assert L.lib().lbfv_set_tile(ctx.h, 8, 3) == L.LBFV_EINVAL
+    assert L.lib().lbfv_set_time_block(ctx.h, 3) == L.LBFV_EINVAL
+    L._check(L.lib().lbfv_set_time_block(ctx.h, 2), ctx.h)      # periodic, no state yet
+    L._check(L.lib().lbfv_set_time_block(ctx.h, 1), ctx.h)
     assert L.lib().dugks_step(ctx.h, -1) == L.LBFV_EINVAL
     assert L.lib().lbfv_step(ctx.h, 4, 1) == L.LBFV_EINVAL
     assert L.lib().lbfv_step(ctx.h, -1, 1) == L.LBFV_EINVAL
@@ -100,6 +103,7 @@ def test_state_errors_before_any_device_work():
     assert L.lib().lbfv_set_wall_from(ctx.h, L.LBFV_SOUTH, -1, 0.0, 0.0) == L.LBFV_EINVAL
     L._check(L.lib().lbfv_set_wall_from(ctx.h, L.LBFV_SOUTH, 3, 0.01, 0.0), ctx.h)
     assert L.lib().dugks_step(ctx.h, 1) == L.LBFV_ESTATE      # north left unset by the switch
+    assert L.lib().lbfv_set_time_block(ctx.h, 2) == L.LBFV_EINVAL  # not doubly periodic
     ctx.set_sides(["periodic"] * 4)
     # replacing one side of a periodic axis leaves the other side unset
     L._check(L.lib().lbfv_set_wall(ctx.h, L.LBFV_WEST, 0.0, 0.0), ctx.h)

@@ -457,3 +457,110 @@ def test_boundary_layer_paper_mesh_against_oracle(dy_min):
         g = gpu_run(w, scheme, 300, f0)
         ext = O.Case(w.xf, w.yf, w.rt, w.tau, w.dt, w.bcs, threads=THREADS, extended=True).run(f0, oscheme, 300)
         assert_fp64(g, ref, ext, f"bl paper dy={dy_min} scheme={scheme}")
+
+
+# ------------------------------------------------------------------ two steps per launch
+def _periodic_workload(nx, ny, seed):
+    xf = I.tanh_faces(nx, 0.9, 0.0, nx / 16.0)
+    yf = I.tanh_faces(ny, 0.6, 0.0, ny / 16.0)
+    rho, ux, uy = I.random_state_fields(ny, nx, seed, amp_u=0.04, amp_rho=0.02)
+    return I.Workload(f"periodic{nx}x{ny}", xf, yf, 0.01, I.cfl_dt(xf, yf, 0.6), ["periodic"] * 4, rho, ux, uy)
+
+
+@pytest.mark.parametrize("nx,ny", [(130, 37), (2, 2), (3, 5), (61, 3), (120, 4), (181, 9)])
+def test_two_steps_per_launch_equal_two_launches(nx, ny):
+    """lbfv_set_time_block(2) on stretched doubly periodic meshes (ragged 60-column strips,
+    meshes narrower than one strip): the same bits as one-step launches for every scheme,
+    FP64 and FP32 deviation storage, odd step counts and graph replays included, and the
+    oracle's result in FP64."""
+    w = _periodic_workload(nx, ny, nx * 7 + ny)
+    ora = oracle_case(w, 2)
+    f0 = perturbed_state(ora, w, 31)
+    for scheme, oscheme in SCHEMES + [(L.LBFV_CENTRAL, O.CENTRAL), (L.LBFV_UPWIND, O.UPWIND)]:
+        for compute, storage in ((L.LBFV_FP64, L.LBFV_STORE_NATIVE), (L.LBFV_FP32, L.LBFV_STORE_DEV_FP32)):
+            for n, tile in ((41, (4, 1)), (150, (7, 2))):
+                outs = []
+                for tb in (1, 2):
+                    with L.Context(w.xf, w.yf, w.tau, w.dt, bcs=w.bcs, compute=compute, storage=storage) as ctx:
+                        ctx.set_f(f0)
+                        ctx.set_time_block(tb)
+                        assert ctx.get_time_block() == tb
+                        ctx.set_tile(*tile)
+                        ctx.step(scheme, n)
+                        outs.append(ctx.get_f())
+                assert np.array_equal(outs[0], outs[1]), (nx, ny, scheme, compute, n)
+                if compute == L.LBFV_FP64 and n == 41:
+                    assert rel(outs[1], ora.run(f0, oscheme, n)) < TOL64
+
+
+def test_time_block_switch_keeps_state_and_falls_back_off_periodic():
+    w = _periodic_workload(130, 20, 5)
+    ora = oracle_case(w)
+    f0 = perturbed_state(ora, w, 37)
+    with L.Context(w.xf, w.yf, w.tau, w.dt, bcs=w.bcs) as ctx:
+        ctx.set_f(f0)
+        for tb in (2, 1, 2):
+            ctx.set_time_block(tb)
+            assert np.array_equal(ctx.get_f(), f0)
+        ctx.dugks_step(10)
+        ctx.set_time_block(1)
+        ctx.dugks_step(10)
+        ctx.set_time_block(2)
+        ctx.dugks_step(11)
+        g = ctx.get_f()
+        r, u, v = ctx.moments()
+        ro, uo, vo = ora.moments(ora.run(f0, O.DUGKS, 31))
+        assert rel(g, ora.run(f0, O.DUGKS, 31)) < TOL64 and rel(u, uo) < TOL64
+        # a non-periodic side: the same state is advanced by one-step launches
+        ctx.set_sides([("wall", 0.0, 0.0), ("outflow", 0), "periodic", "periodic"])
+        ctx.bkg_step(7)
+        assert ctx.get_time_block() == 2
+        wb = I.Workload("wb", w.xf, w.yf, w.tau, w.dt, [("wall", 0.0, 0.0), ("outflow", 0), "periodic", "periodic"],
+                        w.rho, w.ux, w.uy)
+        ref = oracle_case(wb).run(ora.run(f0, O.DUGKS, 31), O.BKG, 7)
+        assert rel(ctx.get_f(), ref) < TOL64
+
+
+def test_time_block_16bit_storage_and_torch_buffers():
+    """16-bit storage: two steps per launch skip the rounding of the intermediate state
+    (so they are not bit-identical to two launches) and stay as close to the FP64 oracle;
+    caller-owned (torch) buffers hold either layout."""
+    w = I.taylor_green(96)
+    ora = oracle_case(w, 2)
+    f0 = ora.init_equilibrium(w.rho, w.ux, w.uy)
+    ref = ora.run(f0, O.DUGKS, 200)
+    for storage in (L.LBFV_STORE_DEV_BF16, L.LBFV_STORE_DEV_FP16):
+        errs = []
+        for tb in (1, 2):
+            with L.Context(w.xf, w.yf, w.tau, w.dt, bcs=w.bcs, compute=L.LBFV_FP32, storage=storage) as ctx:
+                ctx.bind_torch_buffers()
+                ctx.init_equilibrium(w.rho, w.ux, w.uy)
+                ctx.set_time_block(tb)
+                ctx.dugks_step(200)
+                errs.append(u_rel(ora, ctx.get_f(), ref))
+        print(f"16-bit storage={storage}: u error one-step {errs[0]:.2e}, two-step {errs[1]:.2e}")
+        assert errs[1] <= 1.5 * errs[0]
+
+
+def test_autotune_chooses_time_block_and_keeps_state(tmp_path):
+    """On a doubly periodic mesh the autotuner also tries two steps per launch; the state
+    comes back unchanged, stepping afterwards matches the oracle, and a cached entry
+    restores the same time block and shape."""
+    w = _periodic_workload(250, 96, 41)
+    ora = oracle_case(w)
+    f0 = perturbed_state(ora, w, 43)
+    cache = str(tmp_path / "tune.txt")
+    with L.Context(w.xf, w.yf, w.tau, w.dt, bcs=w.bcs) as ctx:
+        ctx.set_f(f0)
+        ms = ctx.autotune(L.LBFV_BKG, 6, cache)
+        assert ms > 0
+        assert np.array_equal(ctx.get_f(), f0)
+        tb, tile = ctx.get_time_block(), ctx.get_tile()
+        print(f"autotune periodic 250x96 BKG: time block {tb}, tile {tile}, {ms:.4f} ms/step")
+        ctx.bkg_step(9)
+        assert rel(ctx.get_f(), ora.run(f0, O.BKG, 9)) < TOL64
+    with L.Context(w.xf, w.yf, w.tau, w.dt, bcs=w.bcs) as ctx:
+        ctx.set_f(f0)
+        ctx.autotune(L.LBFV_BKG, 6, cache)
+        assert ctx.get_time_block() == tb and ctx.get_tile() == tile
+        assert np.array_equal(ctx.get_f(), f0)
