@@ -321,11 +321,21 @@ def boundary_layer_paper(a, stream):
     return out
 
 
+def kernel_code_hash(path=KERNEL_SOURCE):
+    """sha256 of the kernel source with comments and whitespace removed: a profile stays
+    valid across edits of comments only."""
+    import hashlib
+    import re
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return hashlib.sha256(" ".join(text.split()).encode()).hexdigest()
+
+
 def profiled_traffic(tile, time_block, ms_per_step):
     """HBM traffic of the headline kernel from the committed rocprofv3 counter summary:
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the same counters read for a
     plain 1 GiB device copy.  None when the kernel source or the launch shape changed since."""
-    import hashlib
     if not os.path.exists(TRAFFIC_PROFILE):
         return None, None
     kv = {}
@@ -334,8 +344,7 @@ def profiled_traffic(tile, time_block, ms_per_step):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     try:
-        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-        if (kv.get("kernel_source_sha256") != sha or kv.get("tile") != f"{tile[0]},{tile[1]}"
+        if (kv.get("kernel_code_sha256") != kernel_code_hash() or kv.get("tile") != f"{tile[0]},{tile[1]}"
                 or kv.get("time_block", "1") != str(time_block)):
             return None, None
         b = (float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])

@@ -9,15 +9,18 @@
 // LDS and no barriers are used.  Per cell and step the kernel reads the 9
 // stored values once and writes 9 values once; every face value is computed
 // once per wave (the x-face west of each lane, the y-face north of each row).
+// On doubly periodic meshes a second form advances two steps per pass: lane l
+// holds column x0-2+l, lanes 2..61 produce output, and the intermediate step is
+// marched one row behind the first without leaving registers.
 //
 // State layout: SoA [9][ny][pitch] of the stored type S, strip-padded: column c of a
-// row lives in slot (c / 62) * 64 + c % 62, so each 62-column strip owns an aligned
-// block of 64 slots (two pad slots) and every wave stores whole cache lines (partial
-// line stores from two waves into one line cost far more HBM time than the 3 % of
-// padding).  The stored value of direction a is x_a = f~_a - w_a rho0 (rho0 = 0 gives
-// plain f~), optionally divided by w_a for 16-bit storage.  All stages are affine with coefficients
-// that sum to one, so the w_a rho0 offset cancels and every formula below runs
-// unchanged on deviations.
+// row lives in slot (c / W) * 64 + c % W with W = 62 (one step per pass) or 60 (two),
+// so each strip owns an aligned block of 64 slots and every wave stores whole cache
+// lines (partial line stores from two waves into one line cost far more HBM time than
+// the padding).  The stored value of direction a is x_a = f~_a - w_a rho0 (rho0 = 0
+// gives plain f~), optionally divided by w_a for 16-bit storage.  All stages are affine
+// with coefficients that sum to one, so the w_a rho0 offset cancels and every formula
+// below runs unchanged on deviations.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
