@@ -35,7 +35,8 @@ import make_long_horizon as G   # noqa: E402
 pytestmark = pytest.mark.gpu
 TOL64 = 1e-12
 TOL32_U = 1e-5
-BENCH_TILE = (68, 4)            # the timed 4096^2 launch shape
+BENCH_TILE = (32, 2)            # the timed 4096^2 launch shape: rows, waves per block,
+BENCH_TB = 2                    # and two steps per launch
 THREADS = int(os.environ.get("LBFV_ORACLE_THREADS", "8"))
 XX, XY, _W, _REV = O.model()
 
@@ -81,6 +82,7 @@ def test_long_horizon_against_oracle_fixture(case, scheme):
                        storage=storage) as ctx:
             ctx.init_equilibrium(w.rho, w.ux, w.uy)
             if case == "tg4096":
+                ctx.set_time_block(BENCH_TB)
                 ctx.set_tile(*BENCH_TILE)
             ctx.step(SCHEME[scheme], steps)
             tot = ctx.totals()
@@ -91,7 +93,9 @@ def test_long_horizon_against_oracle_fixture(case, scheme):
         results[label] = (ef, eu, et, g)
     ef, eu, et, g = results["fp64"]
     if ext is None:
-        assert ef < TOL64 and eu < TOL64 and et < 1e-13
+        # the totals are sums over all cells in two different orders: their rounding grows
+        # like sqrt(cells)
+        assert ef < TOL64 and eu < TOL64 and et < max(1e-13, 3e-16 * math.sqrt(w.nx * w.ny))
     else:
         # ill-conditioned run: measure both FP64 results against the extended-precision one
         for what, a, b, e in (("f", g, ref, ext), ("u", velocity(g), velocity(ref), velocity(ext))):
@@ -127,10 +131,10 @@ def test_boundary_layer_fp32_1000_steps(scheme, oscheme):
 
 # ------------------------------------------------------------------ 4096^2 windows
 WINDOWS = [(0, 0),            # periodic corner: the window wraps both seams
-           (1000, 58),        # a strip seam (column 62) inside the window
-           (2040, 4060),      # the ragged last strip (4 columns) and the x seam
+           (1000, 58),        # strip seams (60-column strips: columns 60 and 120)
+           (2040, 4060),      # the ragged last strip (16 columns) and the x seam
            (4070, 2000),      # the y seam
-           (67 * 30 - 20, 62 * 33 - 30)]   # a row-block seam (68 rows) and a strip seam
+           (1990, 2016)]      # a row-block seam (32 rows: row 2016) and a strip seam (2040)
 K_WIN, S_WIN = 48, 64
 
 
@@ -159,6 +163,7 @@ def test_tg4096_windows_after_many_steps(scheme, oscheme):
         with L.Context(w.xf, w.yf, w.tau, w.dt, rt=w.rt, bcs=w.bcs, compute=compute,
                        storage=storage) as ctx:
             ctx.set_f(f0)
+            ctx.set_time_block(BENCH_TB)
             if tile:
                 ctx.set_tile(*tile)
             ctx.step(scheme, K_WIN)
@@ -196,6 +201,7 @@ def test_tg4096_2000_steps_physics_and_precisions():
                        storage=storage) as ctx:
             ctx.init_equilibrium(w.rho, w.ux, w.uy)
             m0 = ctx.totals()[0]
+            ctx.set_time_block(BENCH_TB)
             if label == "fp64":
                 ctx.set_tile(*BENCH_TILE)
             ctx.dugks_step(n)
