@@ -79,8 +79,10 @@ typedef struct {
  * default stream).
  *   compute     LBFV_FP64 or LBFV_FP32 arithmetic.
  *   storage     LBFV_STORE_NATIVE stores f~ in the compute type; LBFV_STORE_DEV_* store
- *               the deviation f~_a - w_a rho0 as FP32, BF16 or FP16 (the 16-bit forms
- *               hold (f~_a - w_a rho0)/w_a); DEV_* need FP32 compute.
+ *               the deviation f~_a - F_a as FP32, BF16 or FP16 (the 16-bit forms
+ *               hold (f~_a - F_a)/w_a), where F_a = feq_a(rho0, U0) is the equilibrium
+ *               (Sec. 2.1, Eq. equilibrium) of a reference state, U0 = 0 unless
+ *               lbfv_set_reference_velocity sets it; DEV_* need FP32 compute.
  *   rho0        reference density of the deviation storage.
  *   check_every steps between the FP64 checks (non-finite flag); 0 disables them.
  *   hip_stream  hipStream_t to run on; NULL = the default stream. */
@@ -176,6 +178,17 @@ int lbfv_get_tile(const lbfv_ctx *ctx, int32_t *rows, int32_t *waves_per_block);
  * EINVAL for another value, or for 2 unless all sides are set and periodic. */
 int lbfv_set_time_block(lbfv_ctx *ctx, int32_t steps);
 int lbfv_get_time_block(const lbfv_ctx *ctx, int32_t *steps);
+/* Reference velocity U0 (physical units) of the deviation storage: the state is stored as
+ * f~_a - feq_a(rho0, U0), so a flow near a uniform stream U0 (a free stream past a plate)
+ * keeps small stored values and small FP32 rounding.  The results are those of U0 = 0 up
+ * to that rounding (the step is affine and feq(rho0, U0) is a fixed point of the
+ * collision); the wall bounce-back of Sec. 2.5 takes its momentum term relative to U0.
+ * An existing state is re-encoded in place (rounded once).  EINVAL: non-finite values, or
+ * FP64 compute (native storage, where nothing is gained).  Stepping returns ESTATE while
+ * U0 has a component normal to a symmetry side (feq(rho0, U0) must be mirror-symmetric
+ * there).  Batches always use U0 = 0. */
+int lbfv_set_reference_velocity(lbfv_ctx *ctx, double ux, double uy);
+int lbfv_get_reference_velocity(const lbfv_ctx *ctx, double *ux, double *uy);
 /* Autotuner: times the candidate shapes for `scheme` on this context (the state is
  * saved and restored), keeps the fastest, and records it in a cache file keyed by
  * (gfx arch, scheme, precision, storage, time block, mesh size class).  cache_path NULL: the

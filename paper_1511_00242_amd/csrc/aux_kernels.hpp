@@ -12,11 +12,24 @@ __device__ __forceinline__ int64_t cell_offset(const StepParams<T> &P, int64_t k
     return j * P.pitch + col_slot((int)i, P.strip);
 }
 
-// f~ of an equilibrium state (Omega(feq) = 0): x_a = w_a (rho - rho0 + rho P_a(u / c)),
-// evaluated in FP64 and rounded once to the stored type.
+// The reference state of the deviation storage in FP64: density rho0 and momentum
+// m0 = rho0 U0 / c (all zero for plain storage).  F_a = feq_a(rho0, U0).
+struct RefState {
+    double rho0, m0x, m0y;
+    // rho0 (4.5 (e_a.U0/c)^2 - 1.5 |U0/c|^2)
+    __device__ double q0(int a) const {
+        if (m0x == 0.0 && m0y == 0.0) return 0.0;
+        const double ux = m0x / rho0, uy = m0y / rho0, eu = EX[a] * ux + EY[a] * uy;
+        return rho0 * (4.5 * eu * eu - 1.5 * (ux * ux + uy * uy));
+    }
+    __device__ double F(int a) const { return wgt(a) * (rho0 + (3.0 * (EX[a] * m0x + EY[a] * m0y) + q0(a))); }
+};
+
+// f~ of an equilibrium state (Omega(feq) = 0): x_a = feq_a(rho, u) - F_a, evaluated in FP64
+// and rounded once to the stored type.
 template <typename T, typename S>
 __global__ void init_eq_kernel(StepParams<T> P, int parity, const double *rho, const double *ux,
-                               const double *uy, double inv_c, double rho0) {
+                               const double *uy, double inv_c, RefState R) {
     const int64_t n = (int64_t)P.nx * P.ny;
     S *dst = (S *)P.buf[parity];
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
@@ -25,7 +38,7 @@ __global__ void init_eq_kernel(StepParams<T> P, int parity, const double *rho, c
         S *p = dst + cell_offset(P, k);
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
-            const double x = dfeq<double>(a, r - rho0, r, r * u, r * v, u, v, usq15);
+            const double x = dfeq<double>(a, r - R.rho0, r, r * u - R.m0x, r * v - R.m0y, u, v, usq15, R.q0(a));
             p[a * P.plane] = Storage<S>::store((T)x, a);
         }
     }
@@ -38,7 +51,7 @@ __global__ void init_eq_kernel(StepParams<T> P, int parity, const double *rho, c
 template <typename T, typename S>
 __global__ void init_ce_kernel(StepParams<T> P, int parity, const double *rho, const double *ux, const double *uy,
                                const double *drho, const double *dux, const double *duy, double c, double tau,
-                               double dt, double rho0) {
+                               double dt, RefState R) {
     const int64_t n = (int64_t)P.nx * P.ny;
     S *dst = (S *)P.buf[parity];
     const double inv_c = 1.0 / c, k = 0.5 * dt / tau;
@@ -58,41 +71,41 @@ __global__ void init_ce_kernel(StepParams<T> P, int parity, const double *rho, c
             const double feq = wgt(a) * r * poly;
             const double f = feq - tau * wgt(a) * (Dr * poly + r * dpoly);
             const double ft = f + k * (f - feq);
-            p[a * P.plane] = Storage<S>::store((T)(ft - wgt(a) * rho0), a);
+            p[a * P.plane] = Storage<S>::store((T)(ft - R.F(a)), a);
         }
     }
 }
 
 // host-layout FP64 f~ [9][ny][nx] -> stored deviations
 template <typename T, typename S>
-__global__ void set_f_kernel(StepParams<T> P, int parity, const double *f, double rho0) {
+__global__ void set_f_kernel(StepParams<T> P, int parity, const double *f, RefState R) {
     const int64_t n = (int64_t)P.nx * P.ny;
     S *dst = (S *)P.buf[parity];
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
         S *p = dst + cell_offset(P, k);
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
-            p[a * P.plane] = Storage<S>::store((T)(f[a * n + k] - wgt(a) * rho0), a);
+            p[a * P.plane] = Storage<S>::store((T)(f[a * n + k] - R.F(a)), a);
         }
     }
 }
 
 template <typename T, typename S>
-__global__ void get_f_kernel(StepParams<T> P, int parity, double *f, double rho0) {
+__global__ void get_f_kernel(StepParams<T> P, int parity, double *f, RefState R) {
     const int64_t n = (int64_t)P.nx * P.ny;
     const S *src = (const S *)P.buf[parity];
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
         const S *p = src + cell_offset(P, k);
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
-            f[a * n + k] = (double)Storage<S>::load(p[a * P.plane], a) + wgt(a) * rho0;
+            f[a * n + k] = (double)Storage<S>::load(p[a * P.plane], a) + R.F(a);
         }
     }
 }
 
 // Moments in FP64 from the stored values (Sec. 2.2, Eq. macro_var).
 template <typename T, typename S>
-__device__ __forceinline__ bool cell_moments64(const StepParams<T> &P, const S *src, int64_t k, double rho0,
+__device__ __forceinline__ bool cell_moments64(const StepParams<T> &P, const S *src, int64_t k, const RefState &R,
                                                double c, double &rho, double &ux, double &uy) {
     const S *p = src + cell_offset(P, k);
     double x[9];
@@ -105,20 +118,20 @@ __device__ __forceinline__ bool cell_moments64(const StepParams<T> &P, const S *
     double d = x[0];
 #pragma unroll
     for (int a = 1; a < 9; ++a) d += x[a];
-    rho = rho0 + d;
-    ux = c * (x[1] - x[3] + x[5] - x[6] - x[7] + x[8]) / rho;
-    uy = c * (x[2] - x[4] + x[5] + x[6] - x[7] - x[8]) / rho;
+    rho = R.rho0 + d;
+    ux = c * ((x[1] - x[3] + x[5] - x[6] - x[7] + x[8]) + R.m0x) / rho;
+    uy = c * ((x[2] - x[4] + x[5] + x[6] - x[7] - x[8]) + R.m0y) / rho;
     return finite && isfinite(rho) && isfinite(ux) && isfinite(uy);
 }
 
 template <typename T, typename S>
-__global__ void moments_kernel(StepParams<T> P, int parity, double *rho, double *ux, double *uy, double rho0,
+__global__ void moments_kernel(StepParams<T> P, int parity, double *rho, double *ux, double *uy, RefState R,
                                double c) {
     const int64_t n = (int64_t)P.nx * P.ny;
     const S *src = (const S *)P.buf[parity];
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
         double r, u, v;
-        cell_moments64(P, src, k, rho0, c, r, u, v);
+        cell_moments64(P, src, k, R, c, r, u, v);
         rho[k] = r;
         ux[k] = u;
         uy[k] = v;
@@ -153,14 +166,14 @@ __device__ __forceinline__ void block_sum(double (&v)[RED_N], double (*sh)[RED_B
 template <typename T, typename S>
 __global__ __launch_bounds__(RED_BLOCK) void reduce_kernel(StepParams<T> P, int parity, const double *dxs,
                                                            const double *dys, double *uprev, int mode,
-                                                           double rho0, double c, double *partial) {
+                                                           RefState R, double c, double *partial) {
     __shared__ double sh[RED_N][RED_BLOCK];
     const int64_t n = (int64_t)P.nx * P.ny;
     const S *src = (const S *)P.buf[parity];
     double v[RED_N] = {0, 0, 0, 0, 0, 0};
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
         double r, u, w;
-        const bool ok = cell_moments64(P, src, k, rho0, c, r, u, w);
+        const bool ok = cell_moments64(P, src, k, R, c, r, u, w);
         if (!ok) {
             v[5] += 1.0;
             continue;
@@ -190,6 +203,22 @@ __global__ __launch_bounds__(RED_BLOCK) void reduce_final_kernel(const double *p
     block_sum(v, sh, out);
 }
 
+// Re-encode a state for a new reference state: x_a += F_a(old) - F_a(new), in FP64 and
+// rounded once to the stored type.
+template <typename T, typename S>
+__global__ void reref_kernel(StepParams<T> P, int parity, RefState from, RefState to) {
+    const int64_t n = (int64_t)P.nx * P.ny;
+    S *buf = (S *)P.buf[parity];
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        S *p = buf + cell_offset(P, k);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            const double x = (double)Storage<S>::load(p[a * P.plane], a) + (from.F(a) - to.F(a));
+            p[a * P.plane] = Storage<S>::store((T)x, a);
+        }
+    }
+}
+
 // Copy a state between the two strip layouts (E: an unsigned type of the stored width).
 template <typename E>
 __global__ void relayout_kernel(const E *src, E *dst, int nx, int ny, int64_t pitch_s, int strip_s,
@@ -210,7 +239,7 @@ __global__ void relayout_kernel(const E *src, E *dst, int nx, int ny, int64_t pi
 // per case, written to count[case] (no atomics, nothing to clear beforehand).
 template <typename T, typename S>
 __global__ __launch_bounds__(RED_BLOCK) void batch_nonfinite_kernel(const StepParams<T> *__restrict__ cases,
-                                                                    int parity, double rho0, double c,
+                                                                    int parity, RefState R, double c,
                                                                     int32_t *count) {
     __shared__ int sh[RED_BLOCK];
     const StepParams<T> &P = cases[blockIdx.x];
@@ -219,7 +248,7 @@ __global__ __launch_bounds__(RED_BLOCK) void batch_nonfinite_kernel(const StepPa
     int bad = 0;
     for (int64_t k = threadIdx.x; k < n; k += RED_BLOCK) {
         double r, u, w;
-        bad += cell_moments64(P, src, k, rho0, c, r, u, w) ? 0 : 1;
+        bad += cell_moments64(P, src, k, R, c, r, u, w) ? 0 : 1;
     }
     const int t = threadIdx.x;
     sh[t] = bad;

@@ -17,10 +17,12 @@
 // row lives in slot (c / W) * 64 + c % W with W = 62 (one step per pass) or 60 (two),
 // so each strip owns an aligned block of 64 slots and every wave stores whole cache
 // lines (partial line stores from two waves into one line cost far more HBM time than
-// the padding).  The stored value of direction a is x_a = f~_a - w_a rho0 (rho0 = 0
-// gives plain f~), optionally divided by w_a for 16-bit storage.  All stages are affine
-// with coefficients that sum to one, so the w_a rho0 offset cancels and every formula
-// below runs unchanged on deviations.
+// the padding).  The stored value of direction a is x_a = f~_a - F_a, optionally divided
+// by w_a for 16-bit storage, where F_a = feq_a(rho0, U0) is the equilibrium of a reference
+// state (rho0 = 0 gives plain f~; U0 = 0 unless set).  All stages are affine with
+// coefficients that sum to one and F is a fixed point of the collision, so F cancels and
+// every formula below runs on deviations; the equilibrium takes moments relative to the
+// reference, and the wall bounce-back's momentum term is taken relative to U0 on the host.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -63,6 +65,8 @@ struct StepParams {
     int32_t strip;          // output columns per 64-slot storage block (62, or 60 for two steps per pass)
     T ext[4];               // linear ghost extrapolation factor per side
     T rho0;                 // deviation reference density (0: plain storage)
+    T m0x, m0y;             // reference momentum rho0 U0 / c of the deviation storage (FP32 only)
+    T q0[9];                // rho0 (4.5 (e_a.U0/c)^2 - 1.5 |U0/c|^2), the reference's second-order part
     T hc;                   // h c, h = dt / 2
     T cb;                   // DUGKS: phi = f-bar+ = x + cb (dfeq - x)
     T cd;                   // psi = f~+ = x + cd (dfeq - x) (also BKG's phi)
@@ -158,9 +162,9 @@ template <> struct Acc<float> {
 };
 
 // ---------------------------------------------------------------- equilibrium
-// Deviation of the D2Q9 equilibrium (Sec. 2.1, Eq. equilibrium) from w_a rho0, in
+// Deviation of the D2Q9 equilibrium (Sec. 2.1, Eq. equilibrium) from the reference F_a, in
 // terms of u-hat = u / c (then xi.u / RT = 3 e.u-hat, (xi.u)^2/(2 RT^2) = 4.5 (e.u-hat)^2,
-// |u|^2/(2 RT) = 1.5 |u-hat|^2):  dfeq_a = w_a (drho + rho P_a).
+// |u|^2/(2 RT) = 1.5 |u-hat|^2):  with U0 = 0, dfeq_a = w_a (drho + rho P_a).
 template <typename T>
 __device__ __forceinline__ T usq_term(T ux, T uy) {
     return (T)1.5 * fma(ux, ux, uy * uy);
@@ -193,31 +197,50 @@ __device__ __forceinline__ float wmul<float>(int A, float q) {
 // itself, not as rho times (m / rho): all nine directions would otherwise share the
 // rounding of 1/rho and of rho, and the equilibrium's momentum would drift coherently
 // from step to step (measurable in FP32).
+// Deviation storage holds x_a = f~_a - F_a with F_a = feq_a(rho0, U0): drho = rho - rho0
+// and (mx, my) = rho u/c - rho0 U0/c are deviations, and q0 = rho0 (4.5 (e_a.U0/c)^2 -
+// 1.5 |U0/c|^2) removes the reference's second-order part (0 when U0 = 0).
 template <typename T>
-__device__ __forceinline__ T dfeq(int A, T drho, T rho, T mx, T my, T ux, T uy, T usq15) {
+__device__ __forceinline__ T dfeq(int A, T drho, T rho, T mx, T my, T ux, T uy, T usq15, T q0 = (T)0) {
     const T eu = edot<T>(A, ux, uy);
     const T em = edot<T>(A, mx, my);
     const T q2 = fma((T)4.5 * eu, eu, -usq15);
-    return wmul<T>(A, fma(rho, q2, fma((T)3, em, drho)));
+    return wmul<T>(A, fma(rho, q2, fma((T)3, em, drho) - q0));
 }
 
-// 1 / rho.  FP64: IEEE division.  FP32: the hardware reciprocal (1 ulp); after the
-// first-order equilibrium term is formed from m directly, 1/rho only enters terms of
-// second order in u, where its last bit is far below the FP32 rounding of the state.
+// 1 / rho.  FP64: the hardware reciprocal refined by two Newton steps y += y (1 - r y)
+// (below one ulp; rho is a positive density of order one, so the range scaling of a full
+// IEEE division is not needed).  FP32: the hardware reciprocal (1 ulp).  With the
+// first-order equilibrium term formed from m directly, 1/rho only enters the terms of
+// second order in u, where its last bit is far below the rounding of the state.
 template <typename T>
 __device__ __forceinline__ T recip(T r) { return (T)1 / r; }
 template <>
+__device__ __forceinline__ double recip<double>(double r) {
+    double y = __builtin_amdgcn_rcp(r);
+    double e = fma(-r, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-r, y, 1.0);
+    return fma(y, e, y);
+}
+template <>
 __device__ __forceinline__ float recip<float>(float r) { return __builtin_amdgcn_rcpf(r); }
 
-// Moments of a 9-vector of deviations: drho = sum x, m = rho u-hat = sum e x, u-hat.
+// The reference-velocity terms are compiled for FP32 compute only (FP64 compute stores
+// f~ itself, so its reference state is zero).
+template <typename T>
+constexpr bool kRefVel = sizeof(T) == 4;
+
+// Moments of a 9-vector of deviations: drho = sum x, m = sum e x (the momentum less the
+// reference momentum m0 = rho0 U0 / c), the momentum M = m + m0 = rho u-hat and 1 / rho.
 // COMP: compensated density sum (cell moments; the face moments enter only through the
 // small back-transform weight h / (2 tau + h) and use a plain sum).
 template <typename T>
 struct Mom {
-    T drho, rho, mx, my, ux, uy, usq15;
+    T drho, rho, inv, mx, my, Mx, My, msq15;
 };
 template <typename T, bool COMP = true>
-__device__ __forceinline__ Mom<T> moments(const T (&x)[9], T rho0) {
+__device__ __forceinline__ Mom<T> moments(const T (&x)[9], T rho0, T m0x, T m0y) {
     Mom<T> m;
     if (COMP) {
         Acc<T> acc(x[0]);
@@ -228,17 +251,28 @@ __device__ __forceinline__ Mom<T> moments(const T (&x)[9], T rho0) {
         m.drho = ((x[0] + x[1]) + (x[2] + x[3])) + ((x[4] + x[5]) + (x[6] + x[7])) + x[8];
     }
     m.rho = rho0 + m.drho;
-    const T inv = recip(m.rho);
+    m.inv = recip(m.rho);
     m.mx = x[1] - x[3] + x[5] - x[6] - x[7] + x[8];
     m.my = x[2] - x[4] + x[5] + x[6] - x[7] - x[8];
-    m.ux = m.mx * inv;
-    m.uy = m.my * inv;
-    m.usq15 = usq_term(m.ux, m.uy);
+    if (kRefVel<T>) {
+        m.Mx = m.mx + m0x;
+        m.My = m.my + m0y;
+    } else {
+        m.Mx = m.mx;
+        m.My = m.my;
+    }
+    m.msq15 = usq_term(m.Mx, m.My);
     return m;
 }
+// The equilibrium deviation from the moments: rho P_a's second-order part is
+// rho (4.5 (e.u-hat)^2 - 1.5 |u-hat|^2) = (4.5 (e.M)^2 - 1.5 |M|^2) / rho, so neither u-hat
+// nor e.u-hat is formed.
 template <typename T>
-__device__ __forceinline__ T dfeq(int A, const Mom<T> &m) {
-    return dfeq(A, m.drho, m.rho, m.mx, m.my, m.ux, m.uy, m.usq15);
+__device__ __forceinline__ T dfeq(int A, const Mom<T> &m, T q0) {
+    const T eM = edot<T>(A, m.Mx, m.My);
+    const T em = kRefVel<T> ? edot<T>(A, m.mx, m.my) : eM;
+    const T q = fma((T)4.5 * eM, eM, -m.msq15);
+    return wmul<T>(A, fma(m.inv, q, fma((T)3, em, m.drho) - (kRefVel<T> ? q0 : (T)0)));
 }
 
 // ---------------------------------------------------------------- the strip march
@@ -338,10 +372,10 @@ struct March {
         cell_t(x, phi, psi);
     }
     __device__ __forceinline__ void cell_t(const T (&x)[9], T (&phi)[9], T (&psi)[9]) const {
-        const Mom<T> m = moments(x, P.rho0);
+        const Mom<T> m = moments(x, P.rho0, P.m0x, P.m0y);
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
-            const T d = dfeq(a, m) - x[a];
+            const T d = dfeq(a, m, P.q0[a]) - x[a];
             if (SCHEME == SCHEME_DUGKS) {
                 phi[a] = fma(P.cb, d, x[a]);
                 psi[a] = fma(P.cd, d, x[a]);
@@ -359,7 +393,9 @@ struct March {
         if (k == BC_SYMMETRY) return gm;
         if (k == BC_INFLOW) {
             const T rho = P.bcv[side][0], ux = P.bcv[side][1], uy = P.bcv[side][2];
-            return dfeq(A, rho - P.rho0, rho, rho * ux, rho * uy, ux, uy, usq_term(ux, uy));
+            const T mx = kRefVel<T> ? fma(rho, ux, -P.m0x) : rho * ux;
+            const T my = kRefVel<T> ? fma(rho, uy, -P.m0y) : rho * uy;
+            return dfeq(A, rho - P.rho0, rho, mx, my, ux, uy, usq_term(ux, uy), kRefVel<T> ? P.q0[A] : (T)0);
         }
         if (k == BC_OUTFLOW && P.bcv[side][0] < (T)0.5) return g1;
         return fma(g1 - g2, P.ext[side], g1);   // wall and first-order outflow
@@ -428,11 +464,11 @@ struct March {
     template <int AX>
     __device__ __forceinline__ void face_mix(T (&fb)[9]) const {
         if (SCHEME == SCHEME_DUGKS) {
-            const Mom<T> m = moments<T, false>(fb, P.rho0);
+            const Mom<T> m = moments<T, false>(fb, P.rho0, P.m0x, P.m0y);
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
                 if ((AX == 0 ? EX[a] : EY[a]) != 0) {
-                    const T fe = dfeq(a, m);
+                    const T fe = dfeq(a, m, P.q0[a]);
                     fb[a] = fma(P.m2, fe - fb[a], fb[a]);
                 }
             }

@@ -33,6 +33,7 @@ struct HostCase {
     double wsv[4][2] = {};             // the segment's wall velocity
     int variant = V_F64;
     double rho0 = 0.0;        // 0 for native storage
+    double u0[2] = {0.0, 0.0};   // reference velocity of the deviation storage (physical units)
     int strip = STRIP1;       // output columns per 64-slot block of the current state
     int tblock = 1;           // time steps per launch of the single-case step (1 or 2)
     int64_t pitch = 0, plane = 0;
@@ -54,6 +55,8 @@ struct HostCase {
     bool sides_set() const { return bc[0] >= 0 && bc[1] >= 0 && bc[2] >= 0 && bc[3] >= 0; }
     bool periodic_x() const { return bc[SIDE_W] == BC_PERIODIC; }
     bool periodic_y() const { return bc[SIDE_S] == BC_PERIODIC; }
+    // the reference state in the kernels' units: rho0 and m0 = rho0 U0 / c
+    RefState ref() const { return RefState{rho0, rho0 * u0[0] / c, rho0 * u0[1] / c}; }
 };
 
 #define HIPCHK(expr)                                                                            \
@@ -165,6 +168,7 @@ template <typename T>
 StepParams<T> make_params(const HostCase &h, double ext[4], int scheme = SCHEME_DUGKS) {
     StepParams<T> P;
     memset(&P, 0, sizeof(P));
+    const RefState R = h.ref();
     P.buf[0] = h.buf[0];
     P.buf[1] = h.buf[1];
     P.nx = h.nx;
@@ -177,9 +181,11 @@ StepParams<T> make_params(const HostCase &h, double ext[4], int scheme = SCHEME_
     for (int s = 0; s < 4; ++s) {
         P.bc[s] = h.bc[s];
         P.ext[s] = (T)ext[s];
+        // walls: the bounce-back's momentum term relative to the reference momentum
+        // (F_a - F_rev(a) = 6 w_a e_a.m0 cancels from it)
         if (h.bc[s] == BC_WALL) {
-            P.bcv[s][0] = (T)(6.0 * h.bcval[s][0] / h.c);
-            P.bcv[s][1] = (T)(6.0 * h.bcval[s][1] / h.c);
+            P.bcv[s][0] = (T)(6.0 * (h.bcval[s][0] / h.c - R.m0x));
+            P.bcv[s][1] = (T)(6.0 * (h.bcval[s][1] / h.c - R.m0y));
         } else if (h.bc[s] == BC_INFLOW) {
             P.bcv[s][0] = (T)h.bcval[s][0];
             P.bcv[s][1] = (T)(h.bcval[s][1] / h.c);
@@ -188,11 +194,20 @@ StepParams<T> make_params(const HostCase &h, double ext[4], int scheme = SCHEME_
             P.bcv[s][0] = (T)h.bcval[s][0];
         }
         P.wfrom[s] = h.wfrom[s];
-        P.wsv[s][0] = (T)(6.0 * h.wsv[s][0] / h.c);
-        P.wsv[s][1] = (T)(6.0 * h.wsv[s][1] / h.c);
+        P.wsv[s][0] = (T)(6.0 * (h.wsv[s][0] / h.c - R.m0x));
+        P.wsv[s][1] = (T)(6.0 * (h.wsv[s][1] / h.c - R.m0y));
     }
     const double tau = h.tau, dt = h.dt, hh = 0.5 * dt;
     P.rho0 = (T)h.rho0;
+    P.m0x = (T)R.m0x;
+    P.m0y = (T)R.m0y;
+    if (h.rho0 > 0) {
+        const double ux = h.u0[0] / h.c, uy = h.u0[1] / h.c;
+        for (int a = 0; a < 9; ++a) {
+            const double eu = EX[a] * ux + EY[a] * uy;
+            P.q0[a] = (T)(h.rho0 * (4.5 * eu * eu - 1.5 * (ux * ux + uy * uy)));
+        }
+    }
     P.hc = (T)(hh * h.c);
     P.cb = (T)(3.0 * hh / (2.0 * tau + dt));
     P.cd = (T)(2.0 * dt / (2.0 * tau + dt));
@@ -359,12 +374,12 @@ int resident_waves(void *fn, int wpb) {
 }
 
 // Row-block heights whose wave count fills the resident slots in k whole rounds:
-// few prologue rows re-read and no partial last round.
-std::vector<int> balanced_rows(const HostCase &h, int slots) {
+// few prologue rows re-read and no partial last round (strip: output columns per wave).
+std::vector<int> balanced_rows(const HostCase &h, int slots, int strip, int kmax = 4) {
     std::vector<int> out;
     if (slots <= 0) return out;
-    const int nstrips = (h.nx + h.strip - 1) / h.strip;
-    for (int k = 1; k <= 4; ++k) {
+    const int nstrips = (h.nx + strip - 1) / strip;
+    for (int k = 1; k <= kmax; ++k) {
         const int blocks = (k * slots) / nstrips;   // row blocks per strip
         if (blocks < 1) continue;
         const int r = (h.ny + blocks - 1) / blocks;
@@ -378,7 +393,7 @@ int default_rows(const HostCase &h, int scheme, int wpb) {
     if (cells >= (1 << 22)) {
         // large meshes: one round of resident waves
         const bool bnd = !(h.periodic_x() && h.periodic_y());
-        auto r = balanced_rows(h, resident_waves(step_fn_variant(h.variant, scheme, bnd), wpb));
+        auto r = balanced_rows(h, resident_waves(step_fn_variant(h.variant, scheme, bnd), wpb), STRIP1);
         if (!r.empty()) return r[0];
         return std::min(64, h.ny);
     }
@@ -592,7 +607,7 @@ void launch_reduce_t(lbfv_ctx *c, const double ext[4], int mode) {
     double e[4] = {ext[0], ext[1], ext[2], ext[3]};
     StepParams<T> P = make_params<T>(h, e);
     hipLaunchKernelGGL((reduce_kernel<T, S>), dim3(c->red_blocks), dim3(RED_BLOCK), 0, c->stream, P, h.cur, h.d_dx,
-                       h.d_dy, c->d_uprev, mode, h.rho0, h.c, c->d_partial);
+                       h.d_dy, c->d_uprev, mode, h.ref(), h.c, c->d_partial);
     hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(RED_BLOCK), 0, c->stream, c->d_partial, c->red_blocks,
                        c->d_out);
 }
@@ -639,11 +654,22 @@ int start_check(lbfv_ctx *c) {
     return LBFV_OK;
 }
 
+// a symmetry side (or the symmetry part of a side ending in a wall segment) needs the
+// reference velocity to have no normal component there: F must be mirror-symmetric
+const char *reference_conflict(const HostCase &h) {
+    for (int s = 0; s < 4; ++s) {
+        if (h.bc[s] != BC_SYMMETRY) continue;
+        if (h.u0[s < 2 ? 0 : 1] != 0.0) return "the reference velocity has a component normal to a symmetry side";
+    }
+    return nullptr;
+}
+
 int do_steps(lbfv_ctx *c, int scheme, int32_t n) {
     if (!c) return LBFV_EINVAL;
     if (n < 0) return c->fail(LBFV_EINVAL, "nsteps must be >= 0");
     HostCase &h = c->hc;
     if (!h.sides_set()) return c->fail(LBFV_ESTATE, "all four sides must be set before stepping");
+    if (const char *why = reference_conflict(h)) return c->fail(LBFV_ESTATE, why);
     if (!c->has_state) return c->fail(LBFV_ESTATE, "no initial state (init_equilibrium or set_f first)");
     int st = poll_check(c, false);
     if (st) return st;
@@ -702,7 +728,7 @@ int ce_kernel_t(lbfv_ctx *c, const double *d) {
     const int64_t n = (int64_t)h.nx * h.ny;
     const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
     hipLaunchKernelGGL((init_ce_kernel<T, S>), dim3(blocks), dim3(256), 0, c->stream, P, h.cur, d, d + n, d + 2 * n,
-                       d + 3 * n, d + 6 * n, d + 9 * n, h.c, h.tau, h.dt, h.rho0);
+                       d + 3 * n, d + 6 * n, d + 9 * n, h.c, h.tau, h.dt, h.ref());
     HIPCHK(hipGetLastError());
     return LBFV_OK;
 }
@@ -716,10 +742,10 @@ int state_kernel_t(lbfv_ctx *c, int which, const double *d0, const double *d1, c
     const int64_t n = (int64_t)h.nx * h.ny;
     const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
     switch (which) {
-    case 0: hipLaunchKernelGGL((init_eq_kernel<T, S>), dim3(blocks), dim3(256), 0, c->stream, P, h.cur, d0, d1, d2, 1.0 / h.c, h.rho0); break;
-    case 1: hipLaunchKernelGGL((set_f_kernel<T, S>), dim3(blocks), dim3(256), 0, c->stream, P, h.cur, d0, h.rho0); break;
-    case 2: hipLaunchKernelGGL((get_f_kernel<T, S>), dim3(blocks), dim3(256), 0, c->stream, P, h.cur, dout, h.rho0); break;
-    default: hipLaunchKernelGGL((moments_kernel<T, S>), dim3(blocks), dim3(256), 0, c->stream, P, h.cur, dout, dout + n, dout + 2 * n, h.rho0, h.c); break;
+    case 0: hipLaunchKernelGGL((init_eq_kernel<T, S>), dim3(blocks), dim3(256), 0, c->stream, P, h.cur, d0, d1, d2, 1.0 / h.c, h.ref()); break;
+    case 1: hipLaunchKernelGGL((set_f_kernel<T, S>), dim3(blocks), dim3(256), 0, c->stream, P, h.cur, d0, h.ref()); break;
+    case 2: hipLaunchKernelGGL((get_f_kernel<T, S>), dim3(blocks), dim3(256), 0, c->stream, P, h.cur, dout, h.ref()); break;
+    default: hipLaunchKernelGGL((moments_kernel<T, S>), dim3(blocks), dim3(256), 0, c->stream, P, h.cur, dout, dout + n, dout + 2 * n, h.ref(), h.c); break;
     }
     HIPCHK(hipGetLastError());
     return LBFV_OK;
@@ -732,6 +758,16 @@ int state_kernel(lbfv_ctx *c, int which, const double *d0, const double *d1, con
     case V_BF16: return state_kernel_t<float, __bf16>(c, which, d0, d1, d2, dout);
     default: return state_kernel_t<float, _Float16>(c, which, d0, d1, d2, dout);
     }
+}
+
+template <typename T, typename S>
+void reref_t(lbfv_ctx *c, const RefState &from, const RefState &to) {
+    HostCase &h = c->hc;
+    double ext[4] = {0, 0, 0, 0};
+    StepParams<T> P = make_params<T>(h, ext);
+    const int64_t n = (int64_t)h.nx * h.ny;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL((reref_kernel<T, S>), dim3(blocks), dim3(256), 0, c->stream, P, h.cur, from, to);
 }
 
 // device staging buffer of `count` doubles (freed by the caller)
@@ -1096,6 +1132,44 @@ int lbfv_get_time_block(const lbfv_ctx *c, int32_t *steps) {
     return LBFV_OK;
 }
 
+int lbfv_set_reference_velocity(lbfv_ctx *c, double ux, double uy) {
+    if (!c) return LBFV_EINVAL;
+    HostCase &h = c->hc;
+    if (!std::isfinite(ux) || !std::isfinite(uy))
+        return c->fail(LBFV_EINVAL, "lbfv_set_reference_velocity: velocity must be finite");
+    if (!(h.rho0 > 0))
+        return c->fail(LBFV_EINVAL, "lbfv_set_reference_velocity: needs deviation storage (FP32 compute)");
+    if (ux == h.u0[0] && uy == h.u0[1]) return LBFV_OK;
+    const RefState from = h.ref();
+    const double old[2] = {h.u0[0], h.u0[1]};
+    h.u0[0] = ux;
+    h.u0[1] = uy;
+    if (c->has_state) {
+        int st = poll_check(c, true);
+        if (st) {
+            h.u0[0] = old[0];
+            h.u0[1] = old[1];
+            return st;
+        }
+        const RefState to = h.ref();
+        switch (h.variant) {
+        case V_F32: reref_t<float, float>(c, from, to); break;
+        case V_BF16: reref_t<float, __bf16>(c, from, to); break;
+        default: reref_t<float, _Float16>(c, from, to); break;
+        }
+        HIPCHK(hipGetLastError());
+    }
+    drop_graphs(c);
+    return LBFV_OK;
+}
+
+int lbfv_get_reference_velocity(const lbfv_ctx *c, double *ux, double *uy) {
+    if (!c || !ux || !uy) return LBFV_EINVAL;
+    *ux = c->hc.u0[0];
+    *uy = c->hc.u0[1];
+    return LBFV_OK;
+}
+
 int lbfv_set_tile(lbfv_ctx *c, int32_t rows, int32_t wpb) {
     if (!c) return LBFV_EINVAL;
     if (rows < 0 || (wpb != 0 && wpb != 1 && wpb != 2 && wpb != 4))
@@ -1218,9 +1292,11 @@ extern "C" int lbfv_autotune(lbfv_ctx *c, int scheme, int32_t trial_steps, const
         for (int w : {1, 2, 4}) {
             for (int r : {4, 8, 16, 32, 64, 128, 256})
                 if (r <= h.ny || r == 4) cands.push_back({t, std::min(r, h.ny), w});
-            if (t == 1)
-                for (int r : balanced_rows(h, resident_waves(step_fn_variant(h.variant, scheme, has_boundary(h)), w)))
-                    cands.push_back({t, r, w});
+            // balanced heights; the two-step kernel holds more registers (fewer resident
+            // waves), so its heights of up to 8 rounds are tried
+            void *fn = t == 1 ? step_fn_variant(h.variant, scheme, has_boundary(h)) : step2_fn_variant(h.variant, scheme);
+            for (int r : balanced_rows(h, resident_waves(fn, w), t == 1 ? STRIP1 : STRIP2, t == 1 ? 4 : 8))
+                cands.push_back({t, r, w});
         }
     }
     std::sort(cands.begin(), cands.end());
@@ -1231,12 +1307,16 @@ extern "C" int lbfv_autotune(lbfv_ctx *c, int scheme, int32_t trial_steps, const
         c->wpb = cand[2];
         drop_graphs(c);
         if ((st = do_steps(c, scheme, 2))) break;   // warm-up
-        hipEventRecord(e0, c->stream);
-        if ((st = do_steps(c, scheme, trial_steps))) break;
-        hipEventRecord(e1, c->stream);
-        hipEventSynchronize(e1);
+        hipError_t he = hipEventRecord(e0, c->stream);
+        if (he == hipSuccess && (st = do_steps(c, scheme, trial_steps))) break;
         float t = 0;
-        hipEventElapsedTime(&t, e0, e1);
+        if (he == hipSuccess) he = hipEventRecord(e1, c->stream);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        if (he == hipSuccess) he = hipEventElapsedTime(&t, e0, e1);
+        if (he != hipSuccess) {
+            st = c->fail(LBFV_EHIP, std::string("autotune timing: ") + hipGetErrorString(he));
+            break;
+        }
         const double per = t / trial_steps;
         if (per < best) {
             best = per;
@@ -1249,11 +1329,12 @@ extern "C" int lbfv_autotune(lbfv_ctx *c, int scheme, int32_t trial_steps, const
     h.set_strip(saved_strip);
     h.tblock = saved_tb;
     h.cur = saved_cur;
-    hipMemcpyAsync(h.buf[h.cur], save, h.buffer_bytes(), hipMemcpyDeviceToDevice, c->stream);
-    hipStreamSynchronize(c->stream);
-    hipFree(save);
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    hipError_t re = hipMemcpyAsync(h.buf[h.cur], save, h.buffer_bytes(), hipMemcpyDeviceToDevice, c->stream);
+    if (re == hipSuccess) re = hipStreamSynchronize(c->stream);
+    (void)hipFree(save);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (re != hipSuccess && !st) st = c->fail(LBFV_EHIP, std::string("autotune restore: ") + hipGetErrorString(re));
     c->steps = saved_steps;
     c->steps_at_check = saved_at;
     c->check_every = saved_check;
@@ -1394,10 +1475,10 @@ int batch_state_t(lbfv_batch *b, int ci, int which, const double *d0, const doub
     const int64_t n = (int64_t)h.nx * h.ny;
     const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
     switch (which) {
-    case 0: hipLaunchKernelGGL((init_eq_kernel<T, S>), dim3(blocks), dim3(256), 0, b->stream, P, b->parity, d0, d1, d2, 1.0 / h.c, h.rho0); break;
-    case 1: hipLaunchKernelGGL((set_f_kernel<T, S>), dim3(blocks), dim3(256), 0, b->stream, P, b->parity, d0, h.rho0); break;
-    case 2: hipLaunchKernelGGL((get_f_kernel<T, S>), dim3(blocks), dim3(256), 0, b->stream, P, b->parity, dout, h.rho0); break;
-    default: hipLaunchKernelGGL((moments_kernel<T, S>), dim3(blocks), dim3(256), 0, b->stream, P, b->parity, dout, dout + n, dout + 2 * n, h.rho0, h.c); break;
+    case 0: hipLaunchKernelGGL((init_eq_kernel<T, S>), dim3(blocks), dim3(256), 0, b->stream, P, b->parity, d0, d1, d2, 1.0 / h.c, h.ref()); break;
+    case 1: hipLaunchKernelGGL((set_f_kernel<T, S>), dim3(blocks), dim3(256), 0, b->stream, P, b->parity, d0, h.ref()); break;
+    case 2: hipLaunchKernelGGL((get_f_kernel<T, S>), dim3(blocks), dim3(256), 0, b->stream, P, b->parity, dout, h.ref()); break;
+    default: hipLaunchKernelGGL((moments_kernel<T, S>), dim3(blocks), dim3(256), 0, b->stream, P, b->parity, dout, dout + n, dout + 2 * n, h.ref(), h.c); break;
     }
     if (hipGetLastError() != hipSuccess) return b->fail(LBFV_EHIP, "batch state kernel launch failed");
     return LBFV_OK;
@@ -1523,12 +1604,13 @@ int lbfv_batch_init_equilibrium(lbfv_batch *b, int32_t ci, const double *rho, co
         (void)hipGetLastError();
         return b->fail(LBFV_ENOMEM, "staging");
     }
-    hipMemcpyAsync(d, rho, n * 8, hipMemcpyHostToDevice, b->stream);
-    hipMemcpyAsync(d + n, ux, n * 8, hipMemcpyHostToDevice, b->stream);
-    hipMemcpyAsync(d + 2 * n, uy, n * 8, hipMemcpyHostToDevice, b->stream);
-    int st = batch_state(b, ci, 0, d, d + n, d + 2 * n, nullptr);
-    hipError_t e = hipStreamSynchronize(b->stream);
-    hipFree(d);
+    hipError_t e = hipMemcpyAsync(d, rho, n * 8, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d + n, ux, n * 8, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d + 2 * n, uy, n * 8, hipMemcpyHostToDevice, b->stream);
+    int st = e == hipSuccess ? batch_state(b, ci, 0, d, d + n, d + 2 * n, nullptr) : LBFV_OK;
+    const hipError_t es = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess) e = es;
+    (void)hipFree(d);
     if (st) return st;
     if (e != hipSuccess) return b->fail(LBFV_EHIP, hipGetErrorString(e));
     return LBFV_OK;
@@ -1544,10 +1626,11 @@ int lbfv_batch_set_f(lbfv_batch *b, int32_t ci, const double *f) {
         (void)hipGetLastError();
         return b->fail(LBFV_ENOMEM, "staging");
     }
-    hipMemcpyAsync(d, f, 9 * n * 8, hipMemcpyHostToDevice, b->stream);
-    int st = batch_state(b, ci, 1, d, nullptr, nullptr, nullptr);
-    hipError_t e = hipStreamSynchronize(b->stream);
-    hipFree(d);
+    hipError_t e = hipMemcpyAsync(d, f, 9 * n * 8, hipMemcpyHostToDevice, b->stream);
+    int st = e == hipSuccess ? batch_state(b, ci, 1, d, nullptr, nullptr, nullptr) : LBFV_OK;
+    const hipError_t es = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess) e = es;
+    (void)hipFree(d);
     if (st) return st;
     if (e != hipSuccess) return b->fail(LBFV_EHIP, hipGetErrorString(e));
     return LBFV_OK;
@@ -1563,7 +1646,7 @@ static int batch_fetch(lbfv_batch *b, int32_t ci, int which, double *out, int64_
     hipError_t e = hipSuccess;
     if (!st) e = hipMemcpyAsync(out, d, count * 8, hipMemcpyDeviceToHost, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    hipFree(d);
+    (void)hipFree(d);
     if (st) return st;
     if (e != hipSuccess) return b->fail(LBFV_EHIP, hipGetErrorString(e));
     return LBFV_OK;
@@ -1599,7 +1682,8 @@ int lbfv_batch_nonfinite(lbfv_batch *b, int32_t *count) {
         (void)hipGetLastError();
         return b->fail(LBFV_ENOMEM, "staging");
     }
-    const double c = b->cases[0].c, rho0 = b->cases[0].rho0;
+    const double c = b->cases[0].c;
+    const RefState rho0 = b->cases[0].ref();
     switch (b->variant) {
     case V_F64:
         hipLaunchKernelGGL((batch_nonfinite_kernel<double, double>), dim3(n), dim3(RED_BLOCK), 0, b->stream,

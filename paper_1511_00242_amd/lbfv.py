@@ -34,7 +34,8 @@ EXPORTS = (
     "lbfv_init_chapman_enskog", "lbfv_set_f",
     "lbfv_get_f", "lbfv_bind_buffers", "lbfv_required_bytes", "dugks_step", "bkg_step", "lbfv_step",
     "lbfv_moments", "lbfv_totals", "lbfv_residual", "lbfv_set_tile", "lbfv_get_tile",
-    "lbfv_set_time_block", "lbfv_get_time_block",
+    "lbfv_set_time_block", "lbfv_get_time_block", "lbfv_set_reference_velocity",
+    "lbfv_get_reference_velocity",
     "lbfv_autotune", "lbfv_strerror", "lbfv_last_error", "lbfv_batch_create",
     "lbfv_batch_init_equilibrium", "lbfv_batch_set_f", "lbfv_batch_get_f", "lbfv_batch_step",
     "lbfv_batch_moments", "lbfv_batch_nonfinite", "lbfv_batch_set_shape", "lbfv_batch_info",
@@ -108,6 +109,8 @@ def lib():
             "lbfv_set_tile": ([vp, C.c_int32, C.c_int32], ip),
             "lbfv_set_time_block": ([vp, C.c_int32], ip),
             "lbfv_get_time_block": ([vp, C.POINTER(C.c_int32)], ip),
+            "lbfv_set_reference_velocity": ([vp, C.c_double, C.c_double], ip),
+            "lbfv_get_reference_velocity": ([vp, dp, dp], ip),
             "lbfv_get_tile": ([vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], ip),
             "lbfv_autotune": ([vp, ip, C.c_int32, C.c_char_p, dp], ip),
             "lbfv_strerror": ([ip], C.c_char_p),
@@ -321,6 +324,15 @@ class Context:
         k = C.c_int32()
         _check(lib().lbfv_get_time_block(self.h, C.byref(k)), self.h)
         return k.value
+
+    def set_reference_velocity(self, ux: float, uy: float):
+        """Store the state relative to feq(rho0, (ux, uy)) (deviation storage only)."""
+        _check(lib().lbfv_set_reference_velocity(self.h, float(ux), float(uy)), self.h)
+
+    def get_reference_velocity(self):
+        ux, uy = C.c_double(), C.c_double()
+        _check(lib().lbfv_get_reference_velocity(self.h, C.byref(ux), C.byref(uy)), self.h)
+        return ux.value, uy.value
 
     def autotune(self, scheme: int, trial_steps: int = 20, cache_path=None) -> float:
         ms = C.c_double()

@@ -108,6 +108,24 @@ def test_state_errors_before_any_device_work():
     # replacing one side of a periodic axis leaves the other side unset
     L._check(L.lib().lbfv_set_wall(ctx.h, L.LBFV_WEST, 0.0, 0.0), ctx.h)
     assert L.lib().dugks_step(ctx.h, 1) == L.LBFV_ESTATE
+    # the reference velocity belongs to deviation storage
+    assert L.lib().lbfv_set_reference_velocity(ctx.h, 0.1, 0.0) == L.LBFV_EINVAL
+    ctx.close()
+
+
+def test_reference_velocity_setter():
+    xf, yf = _mesh()
+    ctx = L.Context(xf, yf, 0.1, 0.01, compute=L.LBFV_FP32, storage=L.LBFV_STORE_DEV_FP32)
+    assert L.lib().lbfv_set_reference_velocity(ctx.h, float("nan"), 0.0) == L.LBFV_EINVAL
+    assert ctx.get_reference_velocity() == (0.0, 0.0)
+    ctx.set_reference_velocity(0.1, 0.0)          # no state yet: nothing to re-encode
+    assert ctx.get_reference_velocity() == (0.1, 0.0)
+    ctx.set_sides(["periodic", "periodic", "symmetry", "symmetry"])
+    assert L.lib().dugks_step(ctx.h, 1) == L.LBFV_ESTATE        # no state
+    assert "initial state" in L.lib().lbfv_last_error(ctx.h).decode()
+    ctx.set_reference_velocity(0.1, 0.02)         # normal to the symmetry sides
+    assert L.lib().dugks_step(ctx.h, 1) == L.LBFV_ESTATE
+    assert "symmetry" in L.lib().lbfv_last_error(ctx.h).decode()
     ctx.close()
 
 

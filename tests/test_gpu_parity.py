@@ -564,3 +564,89 @@ def test_autotune_chooses_time_block_and_keeps_state(tmp_path):
         ctx.autotune(L.LBFV_BKG, 6, cache)
         assert ctx.get_time_block() == tb and ctx.get_tile() == tile
         assert np.array_equal(ctx.get_f(), f0)
+
+
+# ------------------------------------------------------------------ reference velocity
+def _fp32_run(w, scheme, n, f0, u0, storage=L.LBFV_STORE_DEV_FP32, tb=1):
+    with L.Context(w.xf, w.yf, w.tau, w.dt, rt=w.rt, bcs=w.bcs, compute=L.LBFV_FP32, storage=storage) as ctx:
+        ctx.set_reference_velocity(*u0)
+        ctx.set_f(f0)
+        if tb != 1:
+            ctx.set_time_block(tb)
+        ctx.step(scheme, n)
+        return ctx.get_f()
+
+
+ALL_SCHEMES = SCHEMES + [(L.LBFV_CENTRAL, O.CENTRAL), (L.LBFV_UPWIND, O.UPWIND)]
+
+
+def test_reference_velocity_paper_flat_plate():
+    """Deviation storage relative to feq(rho0, U0) with U0 the free stream, on the flat-plate
+    mesh of Sec. 3.3 (free stream, outflow, symmetry ahead of the plate, wall segment): FP32
+    within the bar of the oracle, and every stored precision at least as close as with
+    U0 = 0 (the stored values are smaller where the flow is near U0)."""
+    w = I.boundary_layer_paper(0.1)
+    ora = oracle_case(w)
+    f0 = ora.init_equilibrium(w.rho, w.ux, w.uy)
+    u0 = (w.meta["u0"], 0.0)
+    for scheme, oscheme in SCHEMES:
+        ref = ora.run(f0, oscheme, 400)
+        for storage in (L.LBFV_STORE_DEV_FP32, L.LBFV_STORE_DEV_BF16, L.LBFV_STORE_DEV_FP16):
+            e0 = u_rel(ora, _fp32_run(w, scheme, 400, f0, (0.0, 0.0), storage), ref)
+            e1 = u_rel(ora, _fp32_run(w, scheme, 400, f0, u0, storage), ref)
+            print(f"flat plate scheme={scheme} storage={storage}: u error U0=0 {e0:.2e}, "
+                  f"U0=free stream {e1:.2e}", flush=True)
+            assert e1 <= e0
+            if storage == L.LBFV_STORE_DEV_FP32:
+                assert e1 < TOL32_U
+
+
+def test_reference_velocity_moving_wall_inflow_outflow():
+    """A reference velocity along neither axis on a mesh with a moving wall (the
+    bounce-back's momentum term is taken relative to U0), a free-stream side and both
+    outflow orders, from a perturbed state, and in the lid-driven cavity (four walls):
+    FP32 within the bar."""
+    mixed = _mixed_workload()
+    ora_m = oracle_case(mixed)
+    cav = I.cavity(64)
+    ora_c = oracle_case(cav)
+    u0 = (0.03, -0.01)
+    for w, ora, f0, n in ((mixed, ora_m, perturbed_state(ora_m, mixed, 41), 60),
+                          (cav, ora_c, ora_c.init_equilibrium(cav.rho, cav.ux, cav.uy), 300)):
+        for scheme, oscheme in SCHEMES:
+            ref = ora.run(f0, oscheme, n)
+            e0 = u_rel(ora, _fp32_run(w, scheme, n, f0, (0.0, 0.0)), ref)
+            e1 = u_rel(ora, _fp32_run(w, scheme, n, f0, u0), ref)
+            print(f"{w.name} fp32 scheme={scheme} {n} steps: u error U0=0 {e0:.2e}, U0={u0} {e1:.2e}", flush=True)
+            assert e1 < TOL32_U
+
+
+def test_reference_velocity_reencode_moments_and_two_steps():
+    """Changing U0 re-encodes the state (one rounding), the FP64 observables read through
+    it, and two steps per launch stay bit-identical to two launches with U0 set."""
+    w = _periodic_workload(130, 37, 3)
+    ora = oracle_case(w, 2)
+    f0 = perturbed_state(ora, w, 43)
+    with L.Context(w.xf, w.yf, w.tau, w.dt, bcs=w.bcs, compute=L.LBFV_FP32,
+                   storage=L.LBFV_STORE_DEV_FP32) as ctx:
+        ctx.set_f(f0)
+        a = ctx.get_f()
+        ctx.set_reference_velocity(0.04, 0.03)
+        assert ctx.get_reference_velocity() == (0.04, 0.03)
+        b = ctx.get_f()
+        # one more FP32 rounding of values of size |f~ - feq(rho0, U0)|
+        assert np.max(np.abs(b - a)) < 4e-7
+        rho, ux, uy = ctx.moments()
+        r0, u0, v0 = ora.moments(f0)
+        assert np.max(np.abs(rho - r0)) < 1e-6 and np.max(np.abs(ux - u0)) < 1e-6 and np.max(np.abs(uy - v0)) < 1e-6
+        m0 = ctx.totals()[0]
+        ctx.dugks_step(60)
+        ctx.set_reference_velocity(-0.02, 0.01)
+        ctx.dugks_step(61)
+        m1 = ctx.totals()[0]
+        e = u_rel(ora, ctx.get_f(), ora.run(f0, O.DUGKS, 121))
+        print(f"re-encoded run: u {e:.2e}, mass drift {abs(m1 - m0) / m0:.2e}", flush=True)
+        assert e < TOL32_U and abs(m1 - m0) / m0 < 1e-6
+    for scheme, _ in ALL_SCHEMES:
+        outs = [_fp32_run(w, scheme, 41, f0, (0.04, 0.03), tb=tb) for tb in (1, 2)]
+        assert np.array_equal(outs[0], outs[1]), scheme
