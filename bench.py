@@ -26,7 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-HEADLINE_TILE = (70, 2)        # rows per block, waves per block of the timed 4096^2 step, and
+HEADLINE_TILE = (142, 2)        # rows per block, waves per block of the timed 4096^2 step, and
 HEADLINE_TIME_BLOCK = 2        # steps per launch (fixed so that the committed counter profile
                                # describes the same launches)
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_dugks_fp64_taylor_green_4096.txt")

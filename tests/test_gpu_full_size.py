@@ -35,7 +35,7 @@ import make_long_horizon as G   # noqa: E402
 pytestmark = pytest.mark.gpu
 TOL64 = 1e-12
 TOL32_U = 1e-5
-BENCH_TILE = (70, 2)            # the timed 4096^2 launch shape: rows, waves per block,
+BENCH_TILE = (142, 2)            # the timed 4096^2 launch shape: rows, waves per block,
 BENCH_TB = 2                    # and two steps per launch
 THREADS = int(os.environ.get("LBFV_ORACLE_THREADS", "8"))
 XX, XY, _W, _REV = O.model()
@@ -145,7 +145,7 @@ WINDOWS = [(0, 0),            # periodic corner: the window wraps both seams
            (1000, 58),        # strip seams (60-column strips: columns 60 and 120)
            (2040, 4060),      # the ragged last strip (16 columns) and the x seam
            (4070, 2000),      # the y seam
-           (1990, 2016)]      # a row-block seam (70 rows: row 2030) and a strip seam (2040)
+           (1960, 2016)]      # a row-block seam (142 rows: row 1988) and a strip seam (2040)
 K_WIN, S_WIN = 48, 64
 
 
