@@ -138,28 +138,39 @@ __global__ void moments_kernel(StepParams<T> P, int parity, double *rho, double 
     }
 }
 
-// Check / observable reduction.  Per block, in FP64 and a fixed order:
+// Check / observable reduction.  Per block (wavefront butterflies, then the waves in
+// order), in FP64 and a fixed order:
 //   [0] sum rho |V|  [1] sum rho u |V|  [2] sum rho v |V|  [3] sum |u - u_prev|^2
 //   [4] sum |u|^2    [5] number of cells with a non-finite value
 // mode bit 1: residual terms (and u_prev := u).
 constexpr int RED_BLOCK = 256;
 constexpr int RED_N = 6;
 
-__device__ __forceinline__ void block_sum(double (&v)[RED_N], double (*sh)[RED_BLOCK], double *out) {
-    const int t = threadIdx.x;
+// Wavefront butterfly: after it every lane holds the sum of the 64 lanes (each step adds
+// a + b in one lane and b + a in its partner, so the lanes agree bit for bit).
+__device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
-    for (int q = 0; q < RED_N; ++q) sh[q][t] = v[q];
-    __syncthreads();
-    for (int s = RED_BLOCK / 2; s > 0; s >>= 1) {
-        if (t < s) {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+constexpr int RED_WAVES = RED_BLOCK / 64;
+
+// Block sum: a butterfly in each wavefront, then the wave partials in wave order.
+__device__ __forceinline__ void block_sum(double (&v)[RED_N], double (*sh)[RED_WAVES], double *out) {
+    const int t = threadIdx.x, wave = t >> 6;
 #pragma unroll
-            for (int q = 0; q < RED_N; ++q) sh[q][t] += sh[q][t + s];
-        }
-        __syncthreads();
+    for (int q = 0; q < RED_N; ++q) {
+        const double s = wave_sum(v[q]);
+        if ((t & 63) == 0) sh[q][wave] = s;
     }
+    __syncthreads();
     if (t == 0) {
 #pragma unroll
-        for (int q = 0; q < RED_N; ++q) out[q] = sh[q][0];
+        for (int q = 0; q < RED_N; ++q) {
+            double s = sh[q][0];
+            for (int w = 1; w < RED_WAVES; ++w) s += sh[q][w];
+            out[q] = s;
+        }
     }
 }
 
@@ -167,7 +178,7 @@ template <typename T, typename S>
 __global__ __launch_bounds__(RED_BLOCK) void reduce_kernel(StepParams<T> P, int parity, const double *dxs,
                                                            const double *dys, double *uprev, int mode,
                                                            RefState R, double c, double *partial) {
-    __shared__ double sh[RED_N][RED_BLOCK];
+    __shared__ double sh[RED_N][RED_WAVES];
     const int64_t n = (int64_t)P.nx * P.ny;
     const S *src = (const S *)P.buf[parity];
     double v[RED_N] = {0, 0, 0, 0, 0, 0};
@@ -195,7 +206,7 @@ __global__ __launch_bounds__(RED_BLOCK) void reduce_kernel(StepParams<T> P, int 
 }
 
 __global__ __launch_bounds__(RED_BLOCK) void reduce_final_kernel(const double *partial, int nblocks, double *out) {
-    __shared__ double sh[RED_N][RED_BLOCK];
+    __shared__ double sh[RED_N][RED_WAVES];
     double v[RED_N] = {0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nblocks; b += RED_BLOCK)
 #pragma unroll
@@ -241,7 +252,7 @@ template <typename T, typename S>
 __global__ __launch_bounds__(RED_BLOCK) void batch_nonfinite_kernel(const StepParams<T> *__restrict__ cases,
                                                                     int parity, RefState R, double c,
                                                                     int32_t *count) {
-    __shared__ int sh[RED_BLOCK];
+    __shared__ int sh[RED_WAVES];
     const StepParams<T> &P = cases[blockIdx.x];
     const int64_t n = (int64_t)P.nx * P.ny;
     const S *src = (const S *)P.buf[parity];
@@ -251,13 +262,15 @@ __global__ __launch_bounds__(RED_BLOCK) void batch_nonfinite_kernel(const StepPa
         bad += cell_moments64(P, src, k, R, c, r, u, w) ? 0 : 1;
     }
     const int t = threadIdx.x;
-    sh[t] = bad;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) bad += __shfl_xor(bad, o, 64);
+    if ((t & 63) == 0) sh[t >> 6] = bad;
     __syncthreads();
-    for (int s = RED_BLOCK / 2; s > 0; s >>= 1) {
-        if (t < s) sh[t] += sh[t + s];
-        __syncthreads();
+    if (t == 0) {
+        int total = 0;
+        for (int w = 0; w < RED_WAVES; ++w) total += sh[w];
+        count[blockIdx.x] = total;
     }
-    if (t == 0) count[blockIdx.x] = sh[0];
 }
 
 }  // namespace lbfv
