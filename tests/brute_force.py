@@ -283,3 +283,47 @@ def run(xf, yf, sides, tau, dt, scheme, f0, nsteps):
         for _ in range(nsteps):
             f = step(m, f, tau, dt, scheme)
         return [[[f[(i, j)][a] for i in range(m.nx)] for j in range(m.ny)] for a in range(9)]
+
+
+# ------------------------------------------------------------------ the tiny test meshes
+# Stretched meshes with dyadic faces (exact in FP64) covering every side kind; each entry:
+# (x faces, y faces, side specs W, E, S, N as the oracle and the library take them, tau, dt).
+def _dyadic_faces(steps, den=64):
+    out = [Fraction(0)]
+    for s in steps:
+        out.append(out[-1] + Fraction(s, den))
+    return out
+
+
+CASES = {
+    # inflow W, first-order outflow E, symmetry S ending in a moving wall segment, moving lid N
+    "mixed": (_dyadic_faces([8, 9, 10, 11, 12, 13, 14, 15]), _dyadic_faces([9, 9, 10, 11, 12, 11, 10, 8]),
+              [("inflow", 257 / 256, 3 / 128, -1 / 256), ("outflow", 1), ("wall_from", 3, 1 / 64, 0.0, "symmetry"),
+               ("wall", 3 / 64, 0.0)], 3 / 64, 1 / 32),
+    # periodic x, wall S moving in x, zero-order outflow N; dt / tau = 4
+    "channel": (_dyadic_faces([10, 9, 8, 8, 9, 10, 11, 12]), _dyadic_faces([7, 8, 9, 10, 10, 9, 8]),
+                ["periodic", "periodic", ("wall", -1 / 32, 0.0), ("outflow", 0)], 1 / 128, 1 / 32),
+    # symmetry W / E, walls S / N moving in x and y; 7 x 9
+    "box": (_dyadic_faces([9, 10, 11, 12, 11, 10, 9]), _dyadic_faces([8, 8, 9, 9, 10, 10, 9, 9, 8]),
+            ["symmetry", "symmetry", ("wall", 1 / 64, 1 / 128), ("wall", -3 / 64, 0.0)], 1 / 16, 1 / 32),
+    # doubly periodic, stretched
+    "periodic": (_dyadic_faces([8, 12, 9, 11, 10, 8, 13, 9]), _dyadic_faces([11, 9, 8, 12, 10, 9, 8, 10]),
+                 ["periodic"] * 4, 1 / 32, 1 / 32),
+    # walls W (moving in y) and E (at rest), free stream S and N
+    "walls_x": (_dyadic_faces([8, 9, 10, 11, 12, 13, 14, 15]), _dyadic_faces([10] * 8),
+                [("wall", 0.0, 1 / 32), ("wall", 0.0, 0.0), ("inflow", 1.0, 1 / 64, 0.0), ("inflow", 1.0, 1 / 64, 0.0)],
+                1 / 32, 1 / 32),
+}
+
+
+def sides_of(bcs):
+    """Side objects from the side specs the oracle and the library take"""
+    out = []
+    for spec in bcs:
+        if isinstance(spec, str):
+            out.append(Side(spec))
+        elif spec[0] == "wall_from":
+            out.append(Side(spec[4], wall_from=spec[1], seg_u=(spec[2], spec[3])))
+        else:
+            out.append(Side(spec[0], *spec[1:]))
+    return out

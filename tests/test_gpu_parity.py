@@ -6,6 +6,7 @@ over all cells.
 """
 import math
 import os
+import sys
 
 import numpy as np
 import pytest
@@ -13,6 +14,9 @@ import pytest
 from oracle import oracle as O
 from paper_1511_00242_amd import inputs as I
 from paper_1511_00242_amd import lbfv as L
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+import brute_force as BF  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 THREADS = int(os.environ.get("LBFV_ORACLE_THREADS", "8"))
@@ -650,3 +654,46 @@ def test_reference_velocity_reencode_moments_and_two_steps():
     for scheme, _ in ALL_SCHEMES:
         outs = [_fp32_run(w, scheme, 41, f0, (0.04, 0.03), tb=tb) for tb in (1, 2)]
         assert np.array_equal(outs[0], outs[1]), scheme
+
+
+# ------------------------------------------------------------------ brute force on tiny meshes
+def _velocity9(f):
+    ex = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])[:, None, None]
+    ey = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])[:, None, None]
+    rho = f.sum(axis=0)
+    return np.stack([(ex * f).sum(axis=0) / rho, (ey * f).sum(axis=0) / rho])
+
+
+@pytest.mark.parametrize("name", sorted(BF.CASES))
+def test_tiny_meshes_against_brute_force(name):
+    """The library against the independent 60-digit brute force (not the oracle) on tiny
+    stretched meshes with every side kind, all four schemes, five steps: FP64 at two
+    launch shapes and two steps per launch where the mesh allows it, and FP32 storage."""
+    xf, yf, bcs, tau, dt = BF.CASES[name]
+    ny, nx = len(yf) - 1, len(xf) - 1
+    xfl, yfl = np.array([float(v) for v in xf]), np.array([float(v) for v in yf])
+    rng = np.random.default_rng(len(name))
+    rho = 1 + rng.integers(-8, 9, (ny, nx)) / 256
+    ux = rng.integers(-8, 9, (ny, nx)) / 512
+    uy = rng.integers(-8, 9, (ny, nx)) / 512
+    w = I.Workload(f"tiny_{name}", xfl, yfl, tau, dt, bcs, rho, ux, uy)
+    ora = oracle_case(w, 1)
+    f0 = perturbed_state(ora, w, 47, amp=2e-2)
+    periodic = all(b == "periodic" for b in bcs)
+    for scheme in (L.LBFV_DUGKS, L.LBFV_BKG, L.LBFV_CENTRAL, L.LBFV_UPWIND):
+        ref = np.array(BF.run(xf, yf, BF.sides_of(bcs), tau, dt, scheme, f0, 5), dtype=float)
+        for tile, tb in ((4, 1), 1), ((3, 2), 1), ((4, 1), 2):
+            if tb == 2 and not periodic:
+                continue
+            with L.Context(w.xf, w.yf, w.tau, w.dt, bcs=w.bcs) as ctx:
+                ctx.set_f(f0)
+                ctx.set_time_block(tb)
+                ctx.set_tile(*tile)
+                ctx.step(scheme, 5)
+                g = ctx.get_f()
+            e = rel(g, ref)
+            assert e < 1e-13, (name, scheme, tile, tb, e)
+        g32 = gpu_run(w, scheme, 5, f0, compute=L.LBFV_FP32, storage=L.LBFV_STORE_DEV_FP32)
+        e32 = rel(_velocity9(g32), _velocity9(ref))
+        print(f"tiny {name} scheme={scheme}: FP64 {e:.1e}, FP32 u {e32:.1e}", flush=True)
+        assert e32 < TOL32_U

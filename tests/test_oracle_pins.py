@@ -7,6 +7,7 @@ sign, a swapped index or a transposed operand in the oracle fails at least one.
 """
 import math
 import os
+import sys
 import threading
 
 import numpy as np
@@ -14,6 +15,9 @@ import pytest
 
 from oracle import oracle as O
 from paper_1511_00242_amd import inputs as I
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+import brute_force as BF  # noqa: E402
 
 RT = 1.0 / 3.0
 TAU_INF = 2.0 ** 996          # collisionless limit: tau so large that Omega rounds to 0
@@ -674,50 +678,9 @@ def test_extended_precision_build_is_the_same_algorithm():
 # rounding.  (A wrong bounce-back sign, swapped face weights, a reversed trace, the wrong
 # back-transform weight, a zero-order wall ghost or a dropped tangential gradient each move
 # the result by 3e-4 .. 1e-2.)
-def _dyadic_faces(steps, den=64):
-    from fractions import Fraction
-    out = [Fraction(0)]
-    for s in steps:
-        out.append(out[-1] + Fraction(s, den))
-    return out
-
-
-BRUTE_CASES = {
-    # inflow W, first-order outflow E, symmetry S ending in a moving wall segment, moving lid N
-    "mixed": (_dyadic_faces([8, 9, 10, 11, 12, 13, 14, 15]), _dyadic_faces([9, 9, 10, 11, 12, 11, 10, 8]),
-              [("inflow", 257 / 256, 3 / 128, -1 / 256), ("outflow", 1), ("wall_from", 3, 1 / 64, 0.0, "symmetry"),
-               ("wall", 3 / 64, 0.0)], 3 / 64, 1 / 32),
-    # periodic x, wall S moving in x, zero-order outflow N; dt / tau = 4
-    "channel": (_dyadic_faces([10, 9, 8, 8, 9, 10, 11, 12]), _dyadic_faces([7, 8, 9, 10, 10, 9, 8]),
-                ["periodic", "periodic", ("wall", -1 / 32, 0.0), ("outflow", 0)], 1 / 128, 1 / 32),
-    # symmetry W / E, walls S / N moving in x and y; 7 x 9
-    "box": (_dyadic_faces([9, 10, 11, 12, 11, 10, 9]), _dyadic_faces([8, 8, 9, 9, 10, 10, 9, 9, 8]),
-            ["symmetry", "symmetry", ("wall", 1 / 64, 1 / 128), ("wall", -3 / 64, 0.0)], 1 / 16, 1 / 32),
-    # doubly periodic, stretched
-    "periodic": (_dyadic_faces([8, 12, 9, 11, 10, 8, 13, 9]), _dyadic_faces([11, 9, 8, 12, 10, 9, 8, 10]),
-                 ["periodic"] * 4, 1 / 32, 1 / 32),
-    # walls W (moving in y) and E (at rest), free stream S and N
-    "walls_x": (_dyadic_faces([8, 9, 10, 11, 12, 13, 14, 15]), _dyadic_faces([10] * 8),
-                [("wall", 0.0, 1 / 32), ("wall", 0.0, 0.0), ("inflow", 1.0, 1 / 64, 0.0), ("inflow", 1.0, 1 / 64, 0.0)],
-                1 / 32, 1 / 32),
-}
-
-
-def _brute_side(spec):
-    import brute_force as BF
-    if isinstance(spec, str):
-        return BF.Side(spec)
-    if spec[0] == "wall_from":
-        return BF.Side(spec[4], wall_from=spec[1], seg_u=(spec[2], spec[3]))
-    return BF.Side(spec[0], *spec[1:])
-
-
-@pytest.mark.parametrize("name", sorted(BRUTE_CASES))
+@pytest.mark.parametrize("name", sorted(BF.CASES))
 def test_brute_force_tiny_meshes_every_side_kind(name):
-    import sys
-    sys.path.insert(0, os.path.dirname(__file__))
-    import brute_force as BF
-    xf, yf, bcs, tau, dt = BRUTE_CASES[name]
+    xf, yf, bcs, tau, dt = BF.CASES[name]
     ny, nx = len(yf) - 1, len(xf) - 1
     xfl, yfl = np.array([float(v) for v in xf]), np.array([float(v) for v in yf])
     ora = O.Case(xfl, yfl, RT, tau, dt, bcs, threads=1)
@@ -726,7 +689,7 @@ def test_brute_force_tiny_meshes_every_side_kind(name):
     ux = rng.integers(-8, 9, (ny, nx)) / 512
     uy = rng.integers(-8, 9, (ny, nx)) / 512
     f0 = ora.init_equilibrium(rho, ux, uy) + random_f(ny, nx, 3, 0.02) - random_f(ny, nx, 3, 0.0)
-    sides = [_brute_side(s) for s in bcs]
+    sides = BF.sides_of(bcs)
     for scheme in (O.DUGKS, O.BKG, O.CENTRAL, O.UPWIND):
         ref = np.array(BF.run(xf, yf, sides, tau, dt, scheme, f0, 5), dtype=float)
         got = ora.run(f0, scheme, 5)
