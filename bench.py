@@ -123,6 +123,8 @@ def run_batch(steps, warmup, stream):
     b = L.Batch(cases, stream=stream.cuda_stream)
     for i, w in enumerate(cases):
         b.init_equilibrium(i, w.rho, w.ux, w.uy)
+    b.autotune(L.LBFV_DUGKS, 20)              # row-block height of the work list (state kept)
+    graph_steps, rows = b.get_shape()
     cells, items = b.info()
     b.step(L.LBFV_DUGKS, warmup)
     torch.cuda.synchronize()
@@ -151,7 +153,8 @@ def run_batch(steps, warmup, stream):
             torch.cuda.synchronize()
             t_seq[label] += e0.elapsed_time(e1) / 32
             ctx.close()
-    return dict(name="batch96_dugks_fp32dev", cases=len(cases), cells=cells, work_items=items,
+    return dict(name="batch96_dugks_fp32dev", cases=len(cases), cells=cells, work_items=items, rows=rows,
+                graph_steps=graph_steps,
                 ms_per_step=ms, mlups=cells / (ms * 1e-3) / 1e6, alg_gbs=cells * BYTES["f32"] / (ms * 1e-3) / 1e9,
                 alg_frac_of_hbm_peak=cells * BYTES["f32"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                 seq_fp64_ms_per_step=t_seq["fp64"], speedup_vs_seq_fp64=t_seq["fp64"] / ms,

@@ -199,6 +199,7 @@ int lbfv_autotune(lbfv_ctx *ctx, int scheme, int32_t trial_steps, const char *ca
 
 const char *lbfv_strerror(int status);
 const char *lbfv_last_error(const lbfv_ctx *ctx);   /* ctx NULL: last error of this thread */
+const char *lbfv_batch_last_error(const lbfv_batch *b);   /* b NULL: last error of this thread */
 
 /* ------------------------------------------------------------------------------
  * Batched form: many independent cases of uneven size, Reynolds number and boundary
@@ -228,8 +229,17 @@ int lbfv_batch_moments(lbfv_batch *b, int32_t case_id, double *rho, double *ux, 
  * caller-allocated); synchronises the stream.  This is the per-case form of the
  * non-finite check, used to map the stable range of (CFL, dt/tau) (Sec. 3.2). */
 int lbfv_batch_nonfinite(lbfv_batch *b, int32_t *count);
-/* Graph length K (default 100) and rows per row block of the work list (default 8). */
+/* Graph length K (default 100) and rows per row block of the work list (default 8); 0
+ * keeps the current value. */
 int lbfv_batch_set_shape(lbfv_batch *b, int32_t graph_steps, int32_t rows);
+int lbfv_batch_get_shape(const lbfv_batch *b, int32_t *graph_steps, int32_t *rows);
+/* Autotuner of the batch: times the row-block heights 2 ... 64 of the work list for
+ * `scheme` (each as a replay of a graph of trial_steps steps, after one warm-up replay),
+ * keeps the fastest, and restores every case's state and the step parity (the trial steps
+ * leave no trace).  Needs a device copy of the whole state for its duration (ENOMEM
+ * otherwise).  best_ms (nullable) receives the time per step of the choice.  EINVAL for an
+ * unknown scheme or trial_steps < 1. */
+int lbfv_batch_autotune(lbfv_batch *b, int scheme, int32_t trial_steps, double *best_ms);
 int lbfv_batch_info(const lbfv_batch *b, int64_t *total_cells, int32_t *work_items);
 int lbfv_batch_destroy(lbfv_batch *b);
 

@@ -422,6 +422,10 @@ const char *lbfv_last_error(const lbfv_ctx *ctx) {
     return ctx ? ctx->last_error.c_str() : g_last_error.c_str();
 }
 
+const char *lbfv_batch_last_error(const lbfv_batch *b) {
+    return b ? b->last_error.c_str() : g_last_error.c_str();
+}
+
 int lbfv_dt_from_cfl(const lbfv_mesh *mesh, double rt, double cfl, double *dt) {
     if (!mesh || !dt || !mesh->xf || !mesh->yf || mesh->nx < 1 || mesh->ny < 1 || !(rt > 0) || !(cfl > 0)) {
         g_last_error = "lbfv_dt_from_cfl: bad argument";
@@ -1582,6 +1586,86 @@ int lbfv_batch_set_shape(lbfv_batch *b, int32_t graph_steps, int32_t rows) {
         b->rows = rows;
         return batch_build_items(b);
     }
+    return LBFV_OK;
+}
+
+int lbfv_batch_get_shape(const lbfv_batch *b, int32_t *graph_steps, int32_t *rows) {
+    if (!b || !graph_steps || !rows) return LBFV_EINVAL;
+    *graph_steps = b->gsteps;
+    *rows = b->rows;
+    return LBFV_OK;
+}
+
+int lbfv_batch_autotune(lbfv_batch *b, int scheme, int32_t trial_steps, double *best_ms) {
+    if (!b) return LBFV_EINVAL;
+    if (scheme != LBFV_DUGKS && scheme != LBFV_BKG) return b->fail(LBFV_EINVAL, "unknown scheme");
+    if (trial_steps < 1) return b->fail(LBFV_EINVAL, "trial_steps must be >= 1");
+    // save the current state of every case in one staging block
+    size_t total = 0;
+    for (const auto &h : b->cases) total += h.buffer_bytes();
+    char *save = nullptr;
+    if (hipMalloc((void **)&save, total) != hipSuccess) {
+        (void)hipGetLastError();
+        return b->fail(LBFV_ENOMEM, "batch autotune: cannot allocate the state copy");
+    }
+    const int parity0 = b->parity, rows0 = b->rows, gsteps0 = b->gsteps;
+    hipError_t e = hipSuccess;
+    size_t off = 0;
+    for (const auto &h : b->cases) {
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(save + off, h.buf[parity0], h.buffer_bytes(), hipMemcpyDeviceToDevice, b->stream);
+        off += h.buffer_bytes();
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int st = e == hipSuccess ? LBFV_OK : b->fail(LBFV_EHIP, std::string("batch autotune: ") + hipGetErrorString(e));
+    // candidate row-block heights; each is timed as one replay of a graph of ts steps after
+    // a first replay that builds and warms it (ts even, so both replays use one graph)
+    const int ts = trial_steps + (trial_steps & 1);
+    int best_rows = rows0;
+    double best = INFINITY;
+    b->gsteps = ts;
+    for (int r : {2, 4, 8, 16, 32, 64}) {
+        if (st) break;
+        b->rows = r;
+        if ((st = batch_build_items(b))) break;
+        if ((st = lbfv_batch_step(b, scheme, ts))) break;
+        float t = 0;
+        e = hipEventRecord(e0, b->stream);
+        if (e == hipSuccess && (st = lbfv_batch_step(b, scheme, ts))) break;
+        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        if (e != hipSuccess) {
+            st = b->fail(LBFV_EHIP, std::string("batch autotune timing: ") + hipGetErrorString(e));
+            break;
+        }
+        if (t / ts < best) {
+            best = t / ts;
+            best_rows = r;
+        }
+    }
+    // restore the state, the parity and the graph length; keep the fastest height
+    b->gsteps = gsteps0;
+    b->rows = st ? rows0 : best_rows;
+    int st2 = batch_build_items(b);
+    off = 0;
+    hipError_t re = hipSuccess;
+    for (const auto &h : b->cases) {
+        if (re == hipSuccess)
+            re = hipMemcpyAsync(h.buf[parity0], save + off, h.buffer_bytes(), hipMemcpyDeviceToDevice, b->stream);
+        off += h.buffer_bytes();
+    }
+    if (re == hipSuccess) re = hipStreamSynchronize(b->stream);
+    b->parity = parity0;
+    (void)hipFree(save);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) return st;
+    if (st2) return st2;
+    if (re != hipSuccess) return b->fail(LBFV_EHIP, std::string("batch autotune restore: ") + hipGetErrorString(re));
+    if (best_ms) *best_ms = best;
     return LBFV_OK;
 }
 

@@ -39,6 +39,7 @@ EXPORTS = (
     "lbfv_autotune", "lbfv_strerror", "lbfv_last_error", "lbfv_batch_create",
     "lbfv_batch_init_equilibrium", "lbfv_batch_set_f", "lbfv_batch_get_f", "lbfv_batch_step",
     "lbfv_batch_moments", "lbfv_batch_nonfinite", "lbfv_batch_set_shape", "lbfv_batch_info",
+    "lbfv_batch_get_shape", "lbfv_batch_autotune", "lbfv_batch_last_error",
     "lbfv_batch_destroy",
 )
 
@@ -115,6 +116,7 @@ def lib():
             "lbfv_autotune": ([vp, ip, C.c_int32, C.c_char_p, dp], ip),
             "lbfv_strerror": ([ip], C.c_char_p),
             "lbfv_last_error": ([vp], C.c_char_p),
+            "lbfv_batch_last_error": ([vp], C.c_char_p),
             "lbfv_batch_create": ([C.c_int32, C.POINTER(_Case), C.POINTER(_Velset), C.POINTER(_Opts),
                                    C.POINTER(vp)], ip),
             "lbfv_batch_init_equilibrium": ([vp, C.c_int32, dp, dp, dp], ip),
@@ -124,6 +126,8 @@ def lib():
             "lbfv_batch_moments": ([vp, C.c_int32, dp, dp, dp], ip),
             "lbfv_batch_nonfinite": ([vp, C.POINTER(C.c_int32)], ip),
             "lbfv_batch_set_shape": ([vp, C.c_int32, C.c_int32], ip),
+            "lbfv_batch_get_shape": ([vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], ip),
+            "lbfv_batch_autotune": ([vp, ip, C.c_int32, dp], ip),
             "lbfv_batch_info": ([vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)], ip),
             "lbfv_batch_destroy": ([vp], ip),
         }
@@ -140,9 +144,9 @@ def _p(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
-def _check(status: int, handle=None):
+def _check(status: int, handle=None, batch=False):
     if status != LBFV_OK:
-        msg = lib().lbfv_last_error(handle)
+        msg = (lib().lbfv_batch_last_error if batch else lib().lbfv_last_error)(handle)
         raise LbfvError(status, (msg or lib().lbfv_strerror(status)).decode()
                         if isinstance(msg, bytes) else str(msg))
 
@@ -382,37 +386,48 @@ class Batch:
 
     def init_equilibrium(self, i, rho, ux, uy):
         r, u, v = (np.ascontiguousarray(a, dtype=np.float64) for a in (rho, ux, uy))
-        _check(lib().lbfv_batch_init_equilibrium(self.h, int(i), _p(r), _p(u), _p(v)), self.h)
+        _check(lib().lbfv_batch_init_equilibrium(self.h, int(i), _p(r), _p(u), _p(v)), self.h, batch=True)
 
     def set_f(self, i, f):
         f = np.ascontiguousarray(f, dtype=np.float64)
-        _check(lib().lbfv_batch_set_f(self.h, int(i), _p(f)), self.h)
+        _check(lib().lbfv_batch_set_f(self.h, int(i), _p(f)), self.h, batch=True)
 
     def get_f(self, i) -> np.ndarray:
         ny, nx = self.shapes[i]
         f = np.zeros((9, ny, nx))
-        _check(lib().lbfv_batch_get_f(self.h, int(i), _p(f)), self.h)
+        _check(lib().lbfv_batch_get_f(self.h, int(i), _p(f)), self.h, batch=True)
         return f
 
     def step(self, scheme: int, n: int):
-        _check(lib().lbfv_batch_step(self.h, int(scheme), int(n)), self.h)
+        _check(lib().lbfv_batch_step(self.h, int(scheme), int(n)), self.h, batch=True)
 
     def moments(self, i):
         ny, nx = self.shapes[i]
         rho = np.zeros((ny, nx)); ux = np.zeros_like(rho); uy = np.zeros_like(rho)
-        _check(lib().lbfv_batch_moments(self.h, int(i), _p(rho), _p(ux), _p(uy)), self.h)
+        _check(lib().lbfv_batch_moments(self.h, int(i), _p(rho), _p(ux), _p(uy)), self.h, batch=True)
         return rho, ux, uy
 
     def nonfinite(self) -> np.ndarray:
         """Per-case number of cells with a non-finite value (int32 [n])."""
         out = np.zeros(len(self.shapes), dtype=np.int32)
-        _check(lib().lbfv_batch_nonfinite(self.h, out.ctypes.data_as(C.POINTER(C.c_int32))), self.h)
+        _check(lib().lbfv_batch_nonfinite(self.h, out.ctypes.data_as(C.POINTER(C.c_int32))), self.h, batch=True)
         return out
 
     def set_shape(self, graph_steps: int = 0, rows: int = 0):
-        _check(lib().lbfv_batch_set_shape(self.h, int(graph_steps), int(rows)), self.h)
+        _check(lib().lbfv_batch_set_shape(self.h, int(graph_steps), int(rows)), self.h, batch=True)
+
+    def get_shape(self):
+        k, r = C.c_int32(), C.c_int32()
+        _check(lib().lbfv_batch_get_shape(self.h, C.byref(k), C.byref(r)), self.h, batch=True)
+        return k.value, r.value
+
+    def autotune(self, scheme: int, trial_steps: int = 20) -> float:
+        """Pick the work list's row-block height by timing; the state is left unchanged."""
+        ms = C.c_double()
+        _check(lib().lbfv_batch_autotune(self.h, int(scheme), int(trial_steps), C.byref(ms)), self.h, batch=True)
+        return ms.value
 
     def info(self):
         cells, items = C.c_int64(), C.c_int32()
-        _check(lib().lbfv_batch_info(self.h, C.byref(cells), C.byref(items)), self.h)
+        _check(lib().lbfv_batch_info(self.h, C.byref(cells), C.byref(items)), self.h, batch=True)
         return cells.value, items.value

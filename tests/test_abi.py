@@ -68,6 +68,9 @@ def test_null_pointers_are_rejected():
     assert lib.bkg_step(None, 1) == L.LBFV_EINVAL
     assert lib.lbfv_batch_create(0, None, None, None, None) == L.LBFV_EINVAL
     assert lib.lbfv_batch_nonfinite(None, None) == L.LBFV_EINVAL
+    assert lib.lbfv_batch_autotune(None, 0, 10, None) == L.LBFV_EINVAL
+    assert lib.lbfv_batch_get_shape(None, None, None) == L.LBFV_EINVAL
+    assert lib.lbfv_batch_last_error(None) is not None
 
 
 def test_state_errors_before_any_device_work():

@@ -321,6 +321,36 @@ def test_batch_matches_oracle_per_case(compute, storage, tol):
     b.close()
 
 
+def test_batch_autotune_keeps_state_and_errors_name_the_batch():
+    """lbfv_batch_autotune: the state and step parity are unchanged by its trial steps,
+    the chosen height is one of its candidates, and stepping afterwards still matches
+    the oracle (FP64).  A failing batch call reports the batch's own message."""
+    cases = _small_batch()
+    b = L.Batch(cases, compute=L.LBFV_FP64, storage=L.LBFV_STORE_NATIVE)
+    b.set_shape(graph_steps=10, rows=8)
+    refs = []
+    for i, w in enumerate(cases):
+        ora = oracle_case(w, 2)
+        f0 = ora.init_equilibrium(w.rho, w.ux, w.uy)
+        b.set_f(i, f0)
+        refs.append((ora, ora.run(f0, O.DUGKS, 13)))
+    b.step(L.LBFV_DUGKS, 3)                     # odd parity before the autotuner
+    before = [b.get_f(i) for i in range(len(cases))]
+    ms = b.autotune(L.LBFV_DUGKS, 7)
+    k, rows = b.get_shape()
+    print(f"batch autotune: rows {rows}, {ms:.4f} ms/step, graph length {k}")
+    assert rows in (2, 4, 8, 16, 32, 64) and k == 10 and ms > 0
+    for i in range(len(cases)):
+        assert np.array_equal(b.get_f(i), before[i])
+    b.step(L.LBFV_DUGKS, 10)
+    for i, (ora, ref) in enumerate(refs):
+        assert rel(b.get_f(i), ref) < TOL64
+    with pytest.raises(L.LbfvError) as e:
+        b.step(7, 1)
+    assert "unknown scheme" in str(e.value)
+    b.close()
+
+
 # ------------------------------------------------------------------ full-size workload
 @pytest.mark.parametrize("scheme,oscheme", SCHEMES)
 def test_taylor_green_4096_fp64_bench_shape(scheme, oscheme):
