@@ -90,9 +90,10 @@ def timed_steps(ctx, scheme, steps, warmup, stream):
 
 
 def run_single(name, w, scheme, compute, storage, steps, warmup, check_every, stream, tile=None,
-               time_block=1):
+               time_block=1, want_u=False):
     """Time `steps` steps of one workload; a fixed launch shape, or the autotuner's choice
-    of shape and time block (two steps per launch are tried on doubly periodic meshes)."""
+    of shape and time block (two steps per launch are tried on doubly periodic meshes).
+    want_u: also return the final velocity field (FP64 moments) under the key "u"."""
     from paper_1511_00242_amd import lbfv as L
     ctx = L.Context(w.xf, w.yf, w.tau, w.dt, rt=w.rt, bcs=w.bcs, compute=compute, storage=storage,
                     check_every=check_every, stream=stream.cuda_stream)
@@ -108,11 +109,18 @@ def run_single(name, w, scheme, compute, storage, steps, warmup, check_every, st
     rows, wpb = ctx.get_tile()
     tb = ctx.get_time_block()
     tot = ctx.totals()                       # also re-checks for non-finite values
+    u = None
+    if want_u:
+        _, ux, uy = ctx.moments()
+        u = np.stack([ux, uy])
     ctx.close()
     cells = w.nx * w.ny
     per = ms / steps
-    return dict(name=name, ms_per_step=per, mlups=cells / (per * 1e-3) / 1e6, wall_ms=wall_ms,
-                tile=[rows, wpb], time_block=tb, mass=tot[0])
+    out = dict(name=name, ms_per_step=per, mlups=cells / (per * 1e-3) / 1e6, wall_ms=wall_ms,
+               tile=[rows, wpb], time_block=tb, mass=tot[0])
+    if want_u:
+        out["u"] = u
+    return out
 
 
 def run_batch(steps, warmup, stream):
@@ -408,7 +416,12 @@ def main():
 
     w = I.taylor_green(a.n)
     head = run_single("dugks_fp64", w, L.LBFV_DUGKS, L.LBFV_FP64, L.LBFV_STORE_NATIVE, steps, a.warmup,
-                      a.check_every, stream, tile or HEADLINE_TILE, a.time_block if tile else HEADLINE_TIME_BLOCK)
+                      a.check_every, stream, tile or HEADLINE_TILE, a.time_block if tile else HEADLINE_TIME_BLOCK,
+                      want_u=not a.no_variants)
+    # FP64 velocity fields after the same warm-up + timed steps, per scheme: the references
+    # of the reduced-precision variants' error (the FP64 GPU step is itself within 1e-12 of
+    # the oracle in the parity tests)
+    ref_u = {L.LBFV_DUGKS: head.pop("u", None)}
     print(f"[bench] dugks fp64 {a.n}^2: {head['ms_per_step']:.4f} ms/step {head['mlups']:.0f} MLUPS",
           file=sys.stderr, flush=True)
     # the roofline figure divides by the step kernel's own average duration: the same launches
@@ -430,15 +443,27 @@ def main():
         for name, sch, comp, sto, dt in specs:
             if only and name not in only:
                 continue
-            r = run_single(name, w, sch, comp, sto, steps, a.warmup, a.check_every, stream, tile, a.time_block)
+            r = run_single(name, w, sch, comp, sto, steps, a.warmup, a.check_every, stream, tile, a.time_block,
+                           want_u=True)
+            u = r.pop("u")
+            if comp == L.LBFV_FP64:
+                ref_u[sch] = u
+            elif ref_u.get(sch) is not None:
+                ref = ref_u[sch]
+                r["u_rel_l2_vs_fp64"] = float(np.linalg.norm(u - ref) / np.linalg.norm(ref))
             # bytes the method defines per step over the time per step; with two steps per
             # launch the state is read and written once per two steps, so this can pass the
             # HBM peak
             r["alg_gbs"] = cells * BYTES[dt] / (r["ms_per_step"] * 1e-3) / 1e9
             r["alg_frac_of_hbm_peak"] = r["alg_gbs"] / HBM_PEAK_GBS
             r["speedup_vs_dugks_fp64"] = head["ms_per_step"] / r["ms_per_step"]
+            if sch == L.LBFV_BKG and "bkg_fp64" in variants:
+                r["speedup_vs_same_scheme_fp64"] = variants["bkg_fp64"]["ms_per_step"] / r["ms_per_step"]
+            elif sch == L.LBFV_DUGKS:
+                r["speedup_vs_same_scheme_fp64"] = head["ms_per_step"] / r["ms_per_step"]
             variants[name] = r
-            print(f"[bench] {name}: {r['ms_per_step']:.4f} ms/step {r['mlups']:.0f} MLUPS", file=sys.stderr,
+            err = f" u error vs FP64 {r['u_rel_l2_vs_fp64']:.2e}" if "u_rel_l2_vs_fp64" in r else ""
+            print(f"[bench] {name}: {r['ms_per_step']:.4f} ms/step {r['mlups']:.0f} MLUPS{err}", file=sys.stderr,
                   flush=True)
         # the smaller workloads (L2 / Infinity-Cache resident, launch bound): MLUPS only
         small = [("tg32_dugks_fp64", I.taylor_green(32), L.LBFV_DUGKS),
