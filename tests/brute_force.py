@@ -5,9 +5,10 @@ cell by cell and face by face in 60-digit decimal arithmetic (``decimal``; its r
 some 40 orders of magnitude below FP64's, so for FP64 comparisons it is exact), for tiny
 meshes.  (Exact rationals would do too, but their denominators grow with every division
 by a density and make five steps on 8 x 8 cells take hours.)  It follows the paper's
-equations directly and shares nothing with the oracle or the library: every face is an object with its own centre, normal and area, the
-characteristic foot x_b - h xi is a point at which the face's linear reconstruction is
-evaluated, and the update is the literal surface sum of Eq. eq_update.
+equations directly and shares nothing with the oracle or the library: every face is an
+object with its own centre, normal and area, the characteristic foot x_b - h xi is a point
+at which the face's linear reconstruction is evaluated, and the update is the literal
+surface sum of Eq. eq_update.
 
 Paper passages (Zhu, Wang & Guo, arXiv 1511.00242):
   Sec. 2.1, Eq. equilibrium       feq = w rho [1 + xi.u/RT + (xi.u)^2/(2 RT^2) - |u|^2/(2 RT)]
