@@ -252,8 +252,9 @@ __device__ __forceinline__ Mom<T> moments(const T (&x)[9], T rho0, T m0x, T m0y)
     }
     m.rho = rho0 + m.drho;
     m.inv = recip(m.rho);
-    m.mx = x[1] - x[3] + x[5] - x[6] - x[7] + x[8];
-    m.my = x[2] - x[4] + x[5] + x[6] - x[7] - x[8];
+    const T d57 = x[5] - x[7], d86 = x[8] - x[6];   // shared by both components
+    m.mx = ((x[1] - x[3]) + d57) + d86;
+    m.my = ((x[2] - x[4]) + d57) - d86;
     if (kRefVel<T>) {
         m.Mx = m.mx + m0x;
         m.My = m.my + m0y;
