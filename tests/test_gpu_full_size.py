@@ -113,7 +113,7 @@ def test_long_horizon_against_oracle_fixture(case, scheme):
         return results[label][1] if ext is None else rel(velocity(results[label][3]), velocity(ext))
     if case == "bl512":
         # FP32 deviations from w rho0 over 5000 steps of the boundary layer (dt/tau = 118)
-        # end at 1.08e-5, most of it in the free stream, where they are largest; stored
+        # end at about 1.1e-5, most of it in the free stream, where they are largest; stored
         # relative to the free stream they stay within the bar
         assert eu32("fp32dev") < 2.0 * TOL32_U
         assert eu32("fp32ref") < TOL32_U
