@@ -620,14 +620,16 @@ struct March {
     // of straight-line code); PHASE -1 decides at run time.
     template <int PHASE>
     __device__ __forceinline__ void body2(int k, int j0, int j1, T (&Pm)[9], T (&P0)[9], T (&Pp)[9],
-                                          T (&Sm)[9], T (&S0)[9], T (&fS)[9], S (&Rnew)[9], S (&Rnext)[9],
+                                          T (&Sm)[9], T (&S0)[9], T (&fS)[9], S (&R)[9],
                                           T (&Qm2)[9], T (&Qm1)[9], T (&Qk)[9], T (&Um1)[9], T (&Uk)[9],
                                           T (&gS)[9]) {
         // the call for row k+1 needs level-0 phi of row k+2 (with a fixed PHASE it is also
-        // formed after row j1, from a row already loaded, and not used)
+        // formed after row j1, from a wrapped row, and not used).  One row of prefetch: the
+        // row is loaded here and used at the end of the call, after both levels' work; with
+        // the straight-line steady call that hides the latency, and a deeper prefetch costs
+        // more in register moves than it saves.
         const bool need_next = PHASE >= 0 || k < j1;
-        const bool load_real = k + 1 < j1;    // the call after the next needs row k+3
-        load(load_real ? k + 3 : k, Rnew);
+        load(need_next ? k + 2 : k, R);
 
         const int r = row_index(k);
         if (r == 0 && k != j0 - 1) {
@@ -647,7 +649,7 @@ struct March {
             advance(k - 1, Qm2, Qm1, Qk, Um1, gS, w);   // level 2 of row k-1
             store_row(k - 1, w);
         }
-        if (need_next) cell(Rnext, Pm, Sm);
+        if (need_next) cell(R, Pm, Sm);
     }
 
     __device__ __forceinline__ void run(int j0, int j1) {
@@ -701,14 +703,12 @@ struct March {
     __device__ __forceinline__ void run2(int j0, int j1) {
         T PA[9], PB[9], PC[9], SA[9], SB[9], SC[9], fS[9];
         T QA[9], QB[9], QC[9], UA[9], UB[9], UC[9], gS[9];
-        S R0[9], R1[9], R2[9], R3[9];
-        // prologue: level-0 phi of rows j0-2, j0-1, j0 (PA, PB, PC) and psi; row j0+1 is
-        // the first call's next row (R0); the first call prefetches row j0+2
-        load(j0 - 2, R3);
+        S R[9], R1[9], R2[9];
+        // prologue: level-0 phi of rows j0-2, j0-1, j0 (PA, PB, PC) and psi
+        load(j0 - 2, R);
         load(j0 - 1, R1);
         load(j0, R2);
-        load(j0 + 1, R0);
-        cell(R3, PA, SA);
+        cell(R, PA, SA);
         cell(R1, PB, SB);
         cell(R2, PC, SC);
         yface(row_index(j0 - 1), PA, PB, fS);
@@ -718,22 +718,22 @@ struct March {
             // FP64 (one wave per SIMD): the first two calls peeled, so that the scheduler
             // can interleave the steady call's two levels and the next row's cell stage
             // (4 % faster; in FP32 the larger block costs registers and time)
-            body2<0>(j0 - 1, j0, j1, PA, PB, PC, SA, SB, fS, R1, R0, QB, QC, QA, UC, UA, gS);
-            body2<1>(j0, j0, j1, PB, PC, PA, SB, SC, fS, R2, R1, QC, QA, QB, UA, UB, gS);
+            body2<0>(j0 - 1, j0, j1, PA, PB, PC, SA, SB, fS, R, QB, QC, QA, UC, UA, gS);
+            body2<1>(j0, j0, j1, PB, PC, PA, SB, SC, fS, R, QC, QA, QB, UA, UB, gS);
             for (int k = j0 + 1; k <= j1; k += 3) {
-                body2<2>(k, j0, j1, PC, PA, PB, SC, SA, fS, R0, R2, QA, QB, QC, UB, UC, gS);
+                body2<2>(k, j0, j1, PC, PA, PB, SC, SA, fS, R, QA, QB, QC, UB, UC, gS);
                 if (k + 1 > j1) break;
-                body2<2>(k + 1, j0, j1, PA, PB, PC, SA, SB, fS, R1, R0, QB, QC, QA, UC, UA, gS);
+                body2<2>(k + 1, j0, j1, PA, PB, PC, SA, SB, fS, R, QB, QC, QA, UC, UA, gS);
                 if (k + 2 > j1) break;
-                body2<2>(k + 2, j0, j1, PB, PC, PA, SB, SC, fS, R2, R1, QC, QA, QB, UA, UB, gS);
+                body2<2>(k + 2, j0, j1, PB, PC, PA, SB, SC, fS, R, QC, QA, QB, UA, UB, gS);
             }
         } else {
             for (int k = j0 - 1; k <= j1; k += 3) {
-                body2<-1>(k, j0, j1, PA, PB, PC, SA, SB, fS, R1, R0, QB, QC, QA, UC, UA, gS);
+                body2<-1>(k, j0, j1, PA, PB, PC, SA, SB, fS, R, QB, QC, QA, UC, UA, gS);
                 if (k + 1 > j1) break;
-                body2<-1>(k + 1, j0, j1, PB, PC, PA, SB, SC, fS, R2, R1, QC, QA, QB, UA, UB, gS);
+                body2<-1>(k + 1, j0, j1, PB, PC, PA, SB, SC, fS, R, QC, QA, QB, UA, UB, gS);
                 if (k + 2 > j1) break;
-                body2<-1>(k + 2, j0, j1, PC, PA, PB, SC, SA, fS, R0, R2, QA, QB, QC, UB, UC, gS);
+                body2<-1>(k + 2, j0, j1, PC, PA, PB, SC, SA, fS, R, QA, QB, QC, UB, UC, gS);
             }
         }
     }
