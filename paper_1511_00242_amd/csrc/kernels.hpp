@@ -503,16 +503,19 @@ struct March {
         }
     }
 
-    // ---- x-face west of each lane at the current row; sy = cell d/dy of phi
-    __device__ __forceinline__ void xface(const T (&phi)[9], const T (&sy)[9], T (&fb)[9]) const {
+    // ---- x-face west of each lane at the current row; dy = phi(row + 1) - phi(row - 1) and
+    // isy = 1 / (yc_{j+1} - yc_{j-1}), so that the cell d/dy of phi is dy isy (the factor is
+    // applied to the two per-lane coefficients once per row instead of to every direction)
+    __device__ __forceinline__ void xface(const T (&phi)[9], const T (&dy)[9], T isy, T (&fb)[9]) const {
+        const T sL = sLE * isy, sR = sRW * isy;
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
             // left cell's share (1 - c) phi_L - e_y hc (1 - lam) sigma_L, formed in the
             // left lane and shifted right
             T part = fma(-cEe(a), phi[a], phi[a]);
-            if (EY[a] != 0) part = fma(EY[a] > 0 ? -sLE : sLE, sy[a], part);
+            if (EY[a] != 0) part = fma(EY[a] > 0 ? -sL : sL, dy[a], part);
             T v = fma(cWe(a), phi[a], shr1(part));
-            if (EY[a] != 0) v = fma(EY[a] > 0 ? -sRW : sRW, sy[a], v);
+            if (EY[a] != 0) v = fma(EY[a] > 0 ? -sR : sR, dy[a], v);
             fb[a] = v;
         }
     }
@@ -524,15 +527,15 @@ struct March {
                                             const T (&S0)[9], T (&fS)[9], T (&v)[9]) const {
         const int ny = P.ny;
         // x-faces at row r
-        T sy[9];
+        T dy[9];
         const T isy = ldc(P.ym, 2 * (ny + 1) + r);
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
-            if (EY[a] != 0) sy[a] = (Pp[a] - Pm[a]) * isy;
-            else sy[a] = (T)0;
+            if (EY[a] != 0) dy[a] = Pp[a] - Pm[a];
+            else dy[a] = (T)0;
         }
         T fW[9];
-        xface(P0, sy, fW);
+        xface(P0, dy, isy, fW);
         if (ghostW && P.bc[SIDE_W] == BC_WALL)
             bounce<-1, 0>(fW, P.bcv[SIDE_W][0], P.bcv[SIDE_W][1], lane == 1);
         if (ghostW && P.bc[SIDE_W] == BC_SYMMETRY) specular<-1, 0>(fW, lane == 1);
