@@ -1294,8 +1294,9 @@ extern "C" int lbfv_autotune(lbfv_ctx *c, int scheme, int32_t trial_steps, const
     for (int t : {1, 2}) {
         if (t == 2 && has_boundary(h)) continue;
         for (int w : {1, 2, 4}) {
-            for (int r : {4, 8, 16, 32, 64, 128, 256})
-                if (r <= h.ny || r == 4) cands.push_back({t, std::min(r, h.ny), w});
+            // (1 and 2 rows: more waves for small, latency-bound meshes)
+            for (int r : {1, 2, 4, 8, 16, 32, 64, 128, 256})
+                if (r <= h.ny || r == 1) cands.push_back({t, std::min(r, h.ny), w});
             // balanced heights; the two-step kernel holds more registers (fewer resident
             // waves), so its heights of up to 8 rounds are tried
             void *fn = t == 1 ? step_fn_variant(h.variant, scheme, has_boundary(h)) : step2_fn_variant(h.variant, scheme);
