@@ -92,7 +92,7 @@ def timed_steps(ctx, scheme, steps, warmup, stream):
 def run_single(name, w, scheme, compute, storage, steps, warmup, check_every, stream, tile=None,
                time_block=1, want_u=False):
     """Time `steps` steps of one workload; a fixed launch shape, or the autotuner's choice
-    of shape and time block (two steps per launch are tried on doubly periodic meshes).
+    of shape and time block (one or two steps per launch).
     want_u: also return the final velocity field (FP64 moments) under the key "u"."""
     from paper_1511_00242_amd import lbfv as L
     ctx = L.Context(w.xf, w.yf, w.tau, w.dt, rt=w.rt, bcs=w.bcs, compute=compute, storage=storage,
@@ -100,11 +100,11 @@ def run_single(name, w, scheme, compute, storage, steps, warmup, check_every, st
     ctx.bind_torch_buffers()
     ctx.init_equilibrium(w.rho, w.ux, w.uy)
     if tile:
-        if all(b == "periodic" for b in w.bcs):
-            ctx.set_time_block(time_block)
+        ctx.set_time_block(time_block)
         ctx.set_tile(*tile)
     else:
-        ctx.autotune(scheme, 10, os.environ.get("LBFV_TUNE_CACHE"))
+        # small meshes take microseconds per step: longer trials keep the choice out of the noise
+        ctx.autotune(scheme, 10 if w.nx * w.ny >= (1 << 20) else 200, os.environ.get("LBFV_TUNE_CACHE"))
     ms, wall_ms = timed_steps(ctx, scheme, steps, warmup, stream)
     rows, wpb = ctx.get_tile()
     tb = ctx.get_time_block()

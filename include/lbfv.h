@@ -169,13 +169,13 @@ int lbfv_residual(lbfv_ctx *ctx, double *r);
  * through, and wavefronts per workgroup (1, 2 or 4).  0 keeps the current value. */
 int lbfv_set_tile(lbfv_ctx *ctx, int32_t rows, int32_t waves_per_block);
 int lbfv_get_tile(const lbfv_ctx *ctx, int32_t *rows, int32_t *waves_per_block);
-/* Time steps per launch of the single-case step: 1, or 2 on a doubly periodic mesh.  With
- * 2, each wavefront reads its strip of the state once, keeps the intermediate step in
- * registers and writes the second, so a step moves half the HBM bytes; the result is the
- * same, bit for bit, as two one-step launches.  The state moves to a 60-column strip
- * layout (the buffers of lbfv_required_bytes hold either layout).  An odd step count ends
- * with a one-step launch, and one-step launches are used whenever a side is not periodic.
- * EINVAL for another value, or for 2 unless all sides are set and periodic. */
+/* Time steps per launch of the single-case step: 1 or 2.  With 2, each wavefront reads its
+ * strip of the state once, keeps the intermediate step in registers (ghost cells, wall and
+ * symmetry faces of both steps included) and writes the second, so a step moves half the
+ * HBM bytes; the result is the same, bit for bit, as two one-step launches.  The state
+ * moves to a 60-column strip layout (the buffers of lbfv_required_bytes hold either
+ * layout).  An odd step count ends with a one-step launch.  EINVAL for another value, or
+ * for 2 before all four sides are set. */
 int lbfv_set_time_block(lbfv_ctx *ctx, int32_t steps);
 int lbfv_get_time_block(const lbfv_ctx *ctx, int32_t *steps);
 /* Reference velocity U0 (physical units) of the deviation storage: the state is stored as

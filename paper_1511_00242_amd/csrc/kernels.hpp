@@ -9,9 +9,10 @@
 // LDS and no barriers are used.  Per cell and step the kernel reads the 9
 // stored values once and writes 9 values once; every face value is computed
 // once per wave (the x-face west of each lane, the y-face north of each row).
-// On doubly periodic meshes a second form advances two steps per pass: lane l
-// holds column x0-2+l, lanes 2..61 produce output, and the intermediate step is
-// marched one row behind the first without leaving registers.
+// A second form advances two steps per pass: lane l holds column x0-2+l, lanes
+// 2..61 produce output, and the intermediate step is marched one row behind the
+// first without leaving registers (with its own ghost cells where sides are not
+// periodic).
 //
 // State layout: SoA [9][ny][pitch] of the stored type S, strip-padded: column c of a
 // row lives in slot (c / W) * 64 + c % W with W = 62 (one step per pass) or 60 (two),
@@ -291,8 +292,8 @@ __device__ __forceinline__ T dfeq_sub(int A, const Mom<T> &m, T q0, T x) {
 // BND = false compiles out every ghost-cell and bounce-back path; it is used when both
 // axes are periodic (rows and columns then wrap and no wall face exists), which keeps
 // the register budget of the interior loop small.  HALO = 1: one step per pass, lane l
-// holds column x0-1+l; HALO = 2 (periodic meshes only): two steps per pass, lane l holds
-// column x0-2+l and the intermediate step stays in registers.
+// holds column x0-1+l; HALO = 2: two steps per pass, lane l holds column x0-2+l and the
+// intermediate step stays in registers (run2 on doubly periodic meshes, run2b with sides).
 template <typename T, typename S, int SCHEME, bool BND, int HALO = 1>
 struct March {
     const StepParams<T> &P;
@@ -329,16 +330,17 @@ struct March {
         ghostW = BND && !per_x && x0 == 0;
         segS = BND && P.wfrom[SIDE_S] >= 0 && col >= P.wfrom[SIDE_S];
         segN = BND && P.wfrom[SIDE_N] >= 0 && col >= P.wfrom[SIDE_N];
-        laneE = nx - x0 + 1;
+        laneE = nx - x0 + HALO;
         ghostE = BND && !per_x && laneE <= 63;
         const T *lam = P.xm, *id = P.xm + (nx + 1), *is = P.xm + 2 * (nx + 1), *cd = is + nx;
-        // HALO = 1: a halo lane only needs the face it shares with the strip; HALO = 2 (a
-        // periodic axis): every lane advances its own (wrapped) column once, so it takes
+        // HALO = 1: a halo lane only needs the face it shares with the strip; HALO = 2 on a
+        // periodic x axis: every lane advances its own (wrapped) column once, so it takes
         // that column's metrics (the metric arrays hold the seam face at index 0 and nx
-        // with identical values)
+        // with identical values).  HALO = 2 with x sides: the ghost lanes (columns -1, nx)
+        // are refilled at each level, and their faces with the mesh are faces 0 and nx.
         int fE = min(max(col + 1, 0), nx), fW = min(max(col, 0), nx);
         int ci = min(max(col, 0), nx - 1);
-        if (HALO == 2) {
+        if (HALO == 2 && per_x) {
             fW = ccol;
             fE = ccol + 1;
             ci = ccol;
@@ -421,7 +423,7 @@ struct March {
             for (int a = 0; a < 9; ++a) {
                 T g1 = shl1(phi[a]), g2 = shl1(g1);
                 T g = ghost_rule(a, SIDE_W, g1, g2, shl1(phi[MIRX[a]]));
-                phi[a] = lane == 0 ? g : phi[a];
+                phi[a] = lane == HALO - 1 ? g : phi[a];
             }
         }
         if (ghostE) {
@@ -537,8 +539,8 @@ struct March {
         T fW[9];
         xface(P0, dy, isy, fW);
         if (ghostW && P.bc[SIDE_W] == BC_WALL)
-            bounce<-1, 0>(fW, P.bcv[SIDE_W][0], P.bcv[SIDE_W][1], lane == 1);
-        if (ghostW && P.bc[SIDE_W] == BC_SYMMETRY) specular<-1, 0>(fW, lane == 1);
+            bounce<-1, 0>(fW, P.bcv[SIDE_W][0], P.bcv[SIDE_W][1], lane == HALO);
+        if (ghostW && P.bc[SIDE_W] == BC_SYMMETRY) specular<-1, 0>(fW, lane == HALO);
         if (ghostE && P.bc[SIDE_E] == BC_WALL)
             bounce<1, 0>(fW, P.bcv[SIDE_E][0], P.bcv[SIDE_E][1], lane == laneE);
         if (ghostE && P.bc[SIDE_E] == BC_SYMMETRY) specular<1, 0>(fW, lane == laneE);
@@ -740,6 +742,110 @@ struct March {
             }
         }
     }
+
+    // the sides of the south face of the mesh (wall, symmetry, wall segment)
+    __device__ __forceinline__ void south_sides(T (&fb)[9]) const {
+        if (P.bc[SIDE_S] == BC_WALL) bounce<0, -1>(fb, P.bcv[SIDE_S][0], P.bcv[SIDE_S][1], !segS);
+        if (P.bc[SIDE_S] == BC_SYMMETRY) specular<0, -1>(fb, !segS);
+        if (P.wfrom[SIDE_S] >= 0) bounce<0, -1>(fb, P.wsv[SIDE_S][0], P.wsv[SIDE_S][1], segS);
+    }
+    static __device__ __forceinline__ void copy9(T (&d)[9], const T (&s)[9]) {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) d[a] = s[a];
+    }
+
+    // ---- two steps per pass over rows [j0, j1) of a mesh with non-periodic sides
+    // (HALO = 2, BND).  Level-0 updates of rows a .. b (a = j0 - 1, b = j1, clipped to the
+    // mesh on a non-periodic y axis) give level-1 rows in registers; level-1 updates of rows
+    // j0 .. j1 - 1 are stored.  Beyond a non-periodic y side the level-0 and level-1 ghost
+    // rows come from the ghost rule applied to the rows of the same level (so the level-1
+    // update of row 0 waits for level-1 row 1, and that of row ny-1 follows the last
+    // level-0 update), and the x-side ghost lanes are refilled at each level.  Every update
+    // is the one-step march's arithmetic on the same values, so the result is that of two
+    // one-step launches, bit for bit.  Rows move by copies: a three-way unrolled rotation
+    // (as in run2) triples this long boundary code and ran twice as slow.
+    __device__ __forceinline__ void run2b(int j0, int j1) {
+        const int ny = P.ny;
+        const bool clipS = !per_y && j0 == 0;   // level-1 row -1 is a ghost row
+        const bool clipN = !per_y && j1 == ny;  // level-1 row ny is a ghost row
+        const int a = clipS ? 0 : j0 - 1;
+        const int b = clipN ? ny - 1 : j1;
+        const bool ghostS0 = !per_y && a == 0;  // level-0 row a-1 is the ghost row -1
+        T Pm[9], P0[9], Pp[9], S0[9], Sp[9], fS[9];
+        T Qm2[9], Qm1[9], Q0[9], Um1[9], U0[9], gS[9];
+        S R[9], R1[9], R2[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) Qm1[q] = Q0[q] = U0[q] = gS[q] = (T)0;
+        // prologue: level-0 rows a-1, a, a+1 (row a+1 <= ny - 1 is always in the mesh)
+        load(a - 1, R);
+        load(a, R1);
+        load(a + 1, R2);
+        cell(R1, P0, S0);
+        ghost_x(P0);
+        cell(R2, Pp, Sp);
+        ghost_x(Pp);
+        if (ghostS0) {
+            ghost_y(SIDE_S, P0, Pp, Pm);
+        } else {
+            T Sx[9];
+            cell(R, Pm, Sx);
+            ghost_x(Pm);
+        }
+        yface(row_index(a), Pm, P0, fS);
+        if (ghostS0) south_sides(fS);
+        face_mix<1>(fS);
+
+        for (int k = a; k <= b; ++k) {
+            load(k + 2, R);   // (the row index wraps, so the load stays in the buffer)
+            const int r = row_index(k);
+            if (per_y && r == 0 && k != a) {
+                // row 0 entered across the periodic seam: its south face is face 0
+                yface(0, Pm, P0, fS);
+                face_mix<1>(fS);
+            }
+            T v[9];
+            advance(r, Pm, P0, Pp, S0, fS, v);     // level 1 of row k
+            copy9(Qm2, Qm1);
+            copy9(Qm1, Q0);
+            copy9(Um1, U0);
+            cell_t(v, Q0, U0);
+            ghost_x(Q0);
+            if (clipS && k == 1) {
+                // level-1 ghost row -1 from rows 0 and 1, then the south face of row 0
+                ghost_y(SIDE_S, Qm1, Q0, Qm2);
+                yface(0, Qm2, Qm1, gS);
+                south_sides(gS);
+                face_mix<1>(gS);
+            } else if (!clipS && k == j0) {
+                yface(j0, Qm1, Q0, gS);           // level-1 face south of row j0
+                face_mix<1>(gS);
+            }
+            if (k - 1 >= j0) {
+                T w[9];
+                advance(k - 1, Qm2, Qm1, Q0, Um1, gS, w);   // level 2 of row k-1
+                store_row(k - 1, w);
+            }
+            // level-0 rows move up by one; row k+2 becomes the next upper row
+            if (k + 1 <= b) {
+                copy9(Pm, P0);
+                copy9(P0, Pp);
+                copy9(S0, Sp);
+                if (!per_y && k + 2 == ny) {
+                    ghost_y(SIDE_N, P0, Pm, Pp);
+                } else {
+                    cell(R, Pp, Sp);
+                    ghost_x(Pp);
+                }
+            }
+        }
+        if (clipN) {
+            // level-1 ghost row ny from rows ny-1 and ny-2, then the update of row ny-1
+            T Qg[9], w[9];
+            ghost_y(SIDE_N, Q0, Qm1, Qg);
+            advance(ny - 1, Qm1, Q0, Qg, U0, gS, w);
+            store_row(ny - 1, w);
+        }
+    }
 };
 
 // Logical block index such that consecutive logical blocks run on one XCD: the
@@ -787,6 +893,22 @@ __global__ __launch_bounds__(256) void step2_kernel(StepParams<T> P, int parity,
     S *dst = (S *)P.buf[parity ^ 1];
     March<T, S, SCHEME, false, 2> m(P, src, dst, P.strip * sx);
     m.run2(j0, j1);
+}
+
+// Two time steps per launch on a mesh with a non-periodic side (60-column strip layout).
+template <typename T, typename S, int SCHEME>
+__global__ __launch_bounds__(256) void step2b_kernel(StepParams<T> P, int parity, int rows, int nstrips,
+                                                     int nwork) {
+    const int rb = xcd_block();
+    const int wpb = blockDim.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(rb * wpb + (int)(threadIdx.x >> 6));
+    if (w >= nwork) return;
+    const int sx = w % nstrips, sy = w / nstrips;
+    const int j0 = sy * rows, j1 = min(P.ny, j0 + rows);
+    const S *src = (const S *)P.buf[parity];
+    S *dst = (S *)P.buf[parity ^ 1];
+    March<T, S, SCHEME, true, 2> m(P, src, dst, P.strip * sx);
+    m.run2b(j0, j1);
 }
 
 }  // namespace lbfv

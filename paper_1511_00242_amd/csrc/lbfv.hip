@@ -294,15 +294,18 @@ void *step_fn(int scheme, bool bnd) {
     return bnd ? step_fn_b<T, S, true>(scheme) : step_fn_b<T, S, false>(scheme);
 }
 template <typename T, typename S>
-void *step2_fn(int scheme) {
+void *step2_fn(int scheme, bool bnd) {
+    if (bnd)
+        return scheme == SCHEME_BKG ? (void *)step2b_kernel<T, S, SCHEME_BKG> : (void *)step2b_kernel<T, S, SCHEME_DUGKS>;
     return scheme == SCHEME_BKG ? (void *)step2_kernel<T, S, SCHEME_BKG> : (void *)step2_kernel<T, S, SCHEME_DUGKS>;
 }
-void *step2_fn_variant(int variant, int scheme) {
+// two steps per launch; bnd: some side is not periodic
+void *step2_fn_variant(int variant, int scheme, bool bnd) {
     switch (variant) {
-    case V_F64: return step2_fn<double, double>(scheme);
-    case V_F32: return step2_fn<float, float>(scheme);
-    case V_BF16: return step2_fn<float, __bf16>(scheme);
-    default: return step2_fn<float, _Float16>(scheme);
+    case V_F64: return step2_fn<double, double>(scheme, bnd);
+    case V_F32: return step2_fn<float, float>(scheme, bnd);
+    case V_BF16: return step2_fn<float, __bf16>(scheme, bnd);
+    default: return step2_fn<float, _Float16>(scheme, bnd);
     }
 }
 // bnd: some side is not periodic (ghost cells / walls present)
@@ -549,10 +552,10 @@ void current_ext(const HostCase &h, double ext[4]) {
     axis_metrics(h.yf, h.periodic_y(), h.dt, h.c, m, ext[SIDE_S], ext[SIDE_N], s);
 }
 
-// the step kernel of a launch: two steps per launch (periodic meshes in the 60-column
-// layout) or one
+// the step kernel of a launch: two steps per launch (in the 60-column layout; with or
+// without non-periodic sides) or one
 void *launch_fn(const HostCase &h, int scheme, bool two) {
-    return two ? step2_fn_variant(h.variant, scheme) : step_fn_variant(h.variant, scheme, has_boundary(h));
+    return two ? step2_fn_variant(h.variant, scheme, has_boundary(h)) : step_fn_variant(h.variant, scheme, has_boundary(h));
 }
 
 int launch_one(lbfv_ctx *c, int scheme, int parity, const double ext[4], bool two = false) {
@@ -683,8 +686,8 @@ int do_steps(lbfv_ctx *c, int scheme, int32_t n) {
     if (st) return st;
     current_ext(h, ext);
     if (c->rows <= 0) c->rows = default_rows(h, scheme, c->wpb);
-    // two steps per launch while both axes are periodic; an odd step is a one-step launch
-    const bool two = h.tblock == 2 && !has_boundary(h);
+    // two steps per launch when the time block is 2; an odd step is a one-step launch
+    const bool two = h.tblock == 2;
     const int per = two ? 2 : 1;
     while (n > 0) {
         int seg = n;
@@ -1099,8 +1102,8 @@ int lbfv_set_time_block(lbfv_ctx *c, int32_t steps) {
     if (!c) return LBFV_EINVAL;
     HostCase &h = c->hc;
     if (steps != 1 && steps != 2) return c->fail(LBFV_EINVAL, "lbfv_set_time_block: steps must be 1 or 2");
-    if (steps == 2 && !(h.sides_set() && h.periodic_x() && h.periodic_y()))
-        return c->fail(LBFV_EINVAL, "lbfv_set_time_block: two steps per launch need both axes periodic");
+    if (steps == 2 && !h.sides_set())
+        return c->fail(LBFV_EINVAL, "lbfv_set_time_block: set all four sides first");
     const int w = steps == 2 ? STRIP2 : STRIP1;
     if (w != h.strip) {
         if (c->has_state) {
@@ -1262,7 +1265,6 @@ extern "C" int lbfv_autotune(lbfv_ctx *c, int scheme, int32_t trial_steps, const
     int rows, wpb, tb;
     double ms;
     if (cache_lookup(path, key, rows, wpb, ms, tb)) {
-        if (tb == 2 && has_boundary(h)) tb = 1;
         int st = lbfv_set_time_block(c, tb);
         if (st) return st;
         c->rows = std::min(rows, h.ny);
@@ -1288,18 +1290,17 @@ extern "C" int lbfv_autotune(lbfv_ctx *c, int scheme, int32_t trial_steps, const
     int best_r = 0, best_w = 0, best_t = 1;
     double best = INFINITY;
     int st = LBFV_OK;
-    // candidate shapes: (time block, rows, waves per block); two steps per launch only on a
-    // doubly periodic mesh
+    // candidate shapes: (time block, rows, waves per block)
     std::vector<std::array<int, 3>> cands;
     for (int t : {1, 2}) {
-        if (t == 2 && has_boundary(h)) continue;
         for (int w : {1, 2, 4}) {
             // (1 and 2 rows: more waves for small, latency-bound meshes)
             for (int r : {1, 2, 4, 8, 16, 32, 64, 128, 256})
                 if (r <= h.ny || r == 1) cands.push_back({t, std::min(r, h.ny), w});
             // balanced heights; the two-step kernel holds more registers (fewer resident
             // waves), so its heights of up to 8 rounds are tried
-            void *fn = t == 1 ? step_fn_variant(h.variant, scheme, has_boundary(h)) : step2_fn_variant(h.variant, scheme);
+            void *fn = t == 1 ? step_fn_variant(h.variant, scheme, has_boundary(h))
+                              : step2_fn_variant(h.variant, scheme, has_boundary(h));
             for (int r : balanced_rows(h, resident_waves(fn, w), t == 1 ? STRIP1 : STRIP2, t == 1 ? 4 : 8))
                 cands.push_back({t, r, w});
         }

@@ -106,7 +106,7 @@ def test_state_errors_before_any_device_work():
     assert L.lib().lbfv_set_wall_from(ctx.h, L.LBFV_SOUTH, -1, 0.0, 0.0) == L.LBFV_EINVAL
     L._check(L.lib().lbfv_set_wall_from(ctx.h, L.LBFV_SOUTH, 3, 0.01, 0.0), ctx.h)
     assert L.lib().dugks_step(ctx.h, 1) == L.LBFV_ESTATE      # north left unset by the switch
-    assert L.lib().lbfv_set_time_block(ctx.h, 2) == L.LBFV_EINVAL  # not doubly periodic
+    assert L.lib().lbfv_set_time_block(ctx.h, 2) == L.LBFV_EINVAL  # a side is unset
     ctx.set_sides(["periodic"] * 4)
     # replacing one side of a periodic axis leaves the other side unset
     L._check(L.lib().lbfv_set_wall(ctx.h, L.LBFV_WEST, 0.0, 0.0), ctx.h)

@@ -527,6 +527,50 @@ def test_two_steps_per_launch_equal_two_launches(nx, ny):
                     assert rel(outs[1], ora.run(f0, oscheme, n)) < TOL64
 
 
+def _side_sets(nx):
+    """walls on all sides, one periodic axis either way, free stream / both outflow orders,
+    symmetry sides, and wall segments starting at a strip seam or inside a strip"""
+    return [
+        [("wall", 0.0, 0.01), ("wall", 0.0, -0.01), ("wall", 0.02, 0.0), ("wall", -0.01, 0.0)],
+        ["periodic", "periodic", ("wall", 0.0, 0.0), ("inflow", 1.0, 0.02, 0.0)],
+        [("inflow", 1.0, 0.02, 0.0), ("outflow", 0), "periodic", "periodic"],
+        [("inflow", 1.01, 0.03, -0.01), ("outflow", 1), ("wall", 0.02, 0.0), ("outflow", 0)],
+        ["symmetry", ("outflow", 0), ("wall_from", 1, 0.01, 0.0, "symmetry"), "symmetry"],
+        [("inflow", 1.0, 0.05, 0.0), ("outflow", 1), ("wall_from", min(60, nx - 1), 0.0, 0.0, "symmetry"),
+         ("wall_from", min(40, nx - 1), 0.01, 0.0, "symmetry")],
+    ]
+
+
+@pytest.mark.parametrize("nx,ny", [(2, 2), (3, 5), (61, 3), (62, 4), (63, 7), (121, 9), (125, 6), (130, 37)])
+def test_two_steps_per_launch_with_sides_equal_two_launches(nx, ny):
+    """Two steps per launch on meshes with walls, free-stream, outflow and symmetry sides,
+    wall segments and one periodic axis (ragged strips, row blocks touching one or both
+    y sides, meshes narrower than a strip): the same bits as one-step launches for every
+    scheme in FP64 and FP32, odd step counts included, and the oracle's result in FP64."""
+    xf = I.tanh_faces(nx, 0.8, 0.0, nx / 8.0)
+    yf = I.geometric_faces(ny, 0.05, ny / 6.0) if ny > 2 else I.uniform_faces(ny, 0.0, 0.25)
+    rho, ux, uy = I.random_state_fields(ny, nx, nx * 31 + ny, amp_u=0.04, amp_rho=0.02)
+    for k, bcs in enumerate(_side_sets(nx)):
+        w = I.Workload("sides", xf, yf, 0.01, I.cfl_dt(xf, yf, 0.5), bcs, rho, ux, uy)
+        ora = oracle_case(w, 1)
+        f0 = perturbed_state(ora, w, 5 + k)
+        for scheme, oscheme in SCHEMES + [(L.LBFV_CENTRAL, O.CENTRAL), (L.LBFV_UPWIND, O.UPWIND)]:
+            for compute, storage in ((L.LBFV_FP64, L.LBFV_STORE_NATIVE), (L.LBFV_FP32, L.LBFV_STORE_DEV_FP32)):
+                for n, tile in ((9, (1, 1)), (6, (3, 2)), (7, (64, 4))):
+                    outs = []
+                    for tb in (1, 2):
+                        with L.Context(w.xf, w.yf, w.tau, w.dt, bcs=w.bcs, compute=compute,
+                                       storage=storage) as ctx:
+                            ctx.set_f(f0)
+                            ctx.set_time_block(tb)
+                            ctx.set_tile(*tile)
+                            ctx.step(scheme, n)
+                            outs.append(ctx.get_f())
+                    assert np.array_equal(outs[0], outs[1]), (nx, ny, k, scheme, compute, n, tile)
+                    if compute == L.LBFV_FP64 and n == 9 and scheme in (L.LBFV_DUGKS, L.LBFV_BKG):
+                        assert rel(outs[1], ora.run(f0, oscheme, n)) < TOL64, (nx, ny, k, scheme)
+
+
 def test_time_block_switch_keeps_state_and_falls_back_off_periodic():
     w = _periodic_workload(130, 20, 5)
     ora = oracle_case(w)
@@ -545,7 +589,7 @@ def test_time_block_switch_keeps_state_and_falls_back_off_periodic():
         r, u, v = ctx.moments()
         ro, uo, vo = ora.moments(ora.run(f0, O.DUGKS, 31))
         assert rel(g, ora.run(f0, O.DUGKS, 31)) < TOL64 and rel(u, uo) < TOL64
-        # a non-periodic side: the same state is advanced by one-step launches
+        # a non-periodic side: the same state is advanced by the two-step form with sides
         ctx.set_sides([("wall", 0.0, 0.0), ("outflow", 0), "periodic", "periodic"])
         ctx.bkg_step(7)
         assert ctx.get_time_block() == 2
