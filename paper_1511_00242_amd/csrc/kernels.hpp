@@ -907,8 +907,15 @@ __global__ __launch_bounds__(256) void step2b_kernel(StepParams<T> P, int parity
     const int j0 = sy * rows, j1 = min(P.ny, j0 + rows);
     const S *src = (const S *)P.buf[parity];
     S *dst = (S *)P.buf[parity ^ 1];
-    March<T, S, SCHEME, true, 2> m(P, src, dst, P.strip * sx);
-    m.run2b(j0, j1);
+    const int x0 = P.strip * sx;
+    March<T, S, SCHEME, true, 2> m(P, src, dst, x0);
+    // waves whose columns x0-2 .. x0+61 and rows j0-2 .. j1+1 all lie inside the mesh (or
+    // wrap on a periodic axis) need no ghost cells: they take the periodic march, whose rows
+    // rotate without copies
+    const bool inner_x = m.per_x || (x0 >= 2 && x0 + 61 <= P.nx - 1);
+    const bool inner_y = m.per_y || (j0 >= 2 && j1 <= P.ny - 2);
+    if (inner_x && inner_y) m.run2(j0, j1);
+    else m.run2b(j0, j1);
 }
 
 }  // namespace lbfv
