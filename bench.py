@@ -131,15 +131,17 @@ def run_batch(steps, warmup, stream):
     b = L.Batch(cases, stream=stream.cuda_stream)
     for i, w in enumerate(cases):
         b.init_equilibrium(i, w.rho, w.ux, w.uy)
-    b.autotune(L.LBFV_DUGKS, 20)              # row-block height of the work list (state kept)
+    b.autotune(L.LBFV_DUGKS, 20)              # time block and row-block height (state kept)
     graph_steps, rows = b.get_shape()
+    tb = b.get_time_block()
+    per_item = b.get_grid_form()
     cells, items = b.info()
     b.step(L.LBFV_DUGKS, warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    b.step(L.LBFV_DUGKS, steps)             # `steps` is a multiple of the graph length
+    b.step(L.LBFV_DUGKS, steps)             # `steps` is a multiple of the steps of one graph
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
@@ -162,7 +164,7 @@ def run_batch(steps, warmup, stream):
             t_seq[label] += e0.elapsed_time(e1) / 32
             ctx.close()
     return dict(name="batch96_dugks_fp32dev", cases=len(cases), cells=cells, work_items=items, rows=rows,
-                graph_steps=graph_steps,
+                graph_launches=graph_steps, time_block=tb, grid="wave_per_item" if per_item else "resident_waves",
                 ms_per_step=ms, mlups=cells / (ms * 1e-3) / 1e6, alg_gbs=cells * BYTES["f32"] / (ms * 1e-3) / 1e9,
                 alg_frac_of_hbm_peak=cells * BYTES["f32"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                 seq_fp64_ms_per_step=t_seq["fp64"], speedup_vs_seq_fp64=t_seq["fp64"] / ms,
@@ -479,7 +481,7 @@ def main():
             print(f"[bench] {name}: {r['ms_per_step'] * 1e3:.2f} us/step {r['mlups']:.0f} MLUPS", file=sys.stderr,
                   flush=True)
         if not only or "batch" in only:
-            r = run_batch(100, 100, stream)
+            r = run_batch(200, 200, stream)
             variants["batch"] = r
             print(f"[bench] batch: {r['ms_per_step']:.4f} ms/step {r['mlups']:.0f} MLUPS", file=sys.stderr,
                   flush=True)

@@ -172,7 +172,8 @@ int lbfv_get_tile(const lbfv_ctx *ctx, int32_t *rows, int32_t *waves_per_block);
 /* Time steps per launch of the single-case step: 1 or 2.  With 2, each wavefront reads its
  * strip of the state once, keeps the intermediate step in registers (ghost cells, wall and
  * symmetry faces of both steps included) and writes the second, so a step moves half the
- * HBM bytes; the result is the same, bit for bit, as two one-step launches.  The state
+ * HBM bytes; the result is the same, bit for bit, as two one-step launches (with 16-bit
+ * storage the intermediate step is not rounded to 16 bits, so the two differ).  The state
  * moves to a 60-column strip layout (the buffers of lbfv_required_bytes hold either
  * layout).  An odd step count ends with a one-step launch.  EINVAL for another value, or
  * for 2 before all four sides are set. */
@@ -233,12 +234,28 @@ int lbfv_batch_nonfinite(lbfv_batch *b, int32_t *count);
  * keeps the current value. */
 int lbfv_batch_set_shape(lbfv_batch *b, int32_t graph_steps, int32_t rows);
 int lbfv_batch_get_shape(const lbfv_batch *b, int32_t *graph_steps, int32_t *rows);
-/* Autotuner of the batch: times the row-block heights 2 ... 64 of the work list for
- * `scheme` (each as a replay of a graph of trial_steps steps, after one warm-up replay),
+/* Grid form of the batch's launches: 0 (default) launches the waves that fit on the device
+ * at once, which walk the work list with a stride; 1 launches one wave per work item, so
+ * that the hardware gives each freed slot the next block.  Results are the same either way.
+ * EINVAL for another value. */
+int lbfv_batch_set_grid_form(lbfv_batch *b, int32_t wave_per_item);
+int lbfv_batch_get_grid_form(const lbfv_batch *b, int32_t *wave_per_item);
+/* Time steps per launch of the batch: 1 (default) or 2, as lbfv_set_time_block for one
+ * case: with 2 every case moves to the 60-column strip layout, each launch advances every
+ * case by two steps with the intermediate step in registers, a graph of K launches by 2K
+ * steps, and an odd step count ends with a one-step launch; the result is the same, bit
+ * for bit, as with 1 (16-bit storage: as for lbfv_set_time_block).  Synchronises the
+ * stream.  EINVAL for another value. */
+int lbfv_batch_set_time_block(lbfv_batch *b, int32_t steps);
+int lbfv_batch_get_time_block(const lbfv_batch *b, int32_t *steps);
+/* Autotuner of the batch: times the time blocks 1 and 2, row-block heights of the work
+ * list (2, 4, ..., 64 and the three a cost model of whole rounds of resident waves ranks
+ * best) and two grid forms (the resident waves walking the list, or one wave per item) for
+ * `scheme`, each as a replay of a graph of trial_steps launches after one warm-up replay;
  * keeps the fastest, and restores every case's state and the step parity (the trial steps
- * leave no trace).  Needs a device copy of the whole state for its duration (ENOMEM
- * otherwise).  best_ms (nullable) receives the time per step of the choice.  EINVAL for an
- * unknown scheme or trial_steps < 1. */
+ * leave no trace).  Needs a device copy of the whole state for its
+ * duration (ENOMEM otherwise).  best_ms (nullable) receives the time per step of the
+ * choice.  EINVAL for an unknown scheme or trial_steps < 1. */
 int lbfv_batch_autotune(lbfv_batch *b, int scheme, int32_t trial_steps, double *best_ms);
 int lbfv_batch_info(const lbfv_batch *b, int64_t *total_cells, int32_t *work_items);
 int lbfv_batch_destroy(lbfv_batch *b);

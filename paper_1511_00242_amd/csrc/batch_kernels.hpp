@@ -32,4 +32,32 @@ __global__ __launch_bounds__(256) void batch_kernel(const StepParams<T> *__restr
     }
 }
 
+// Two time steps per launch of the batched form (every case in the 60-column strip
+// layout): a wave whose strip and row block need no ghost cells takes the periodic
+// march, the others the march with level-1 ghost rows and lanes, as in the single-case
+// two-step kernel.
+template <typename T, typename S, int SCHEME, bool BND>
+__global__ __launch_bounds__(256) void batch2_kernel(const StepParams<T> *__restrict__ cases,
+                                                     const BatchItem *__restrict__ items, int nitems,
+                                                     int parity) {
+    const int wpb = blockDim.x >> 6;
+    const int nw = gridDim.x * wpb;
+    int w = __builtin_amdgcn_readfirstlane(xcd_block() * wpb + (int)(threadIdx.x >> 6));
+    for (; w < nitems; w += nw) {
+        const BatchItem it = items[w];
+        const StepParams<T> &P = cases[it.c];
+        const S *src = (const S *)P.buf[parity];
+        S *dst = (S *)P.buf[parity ^ 1];
+        March<T, S, SCHEME, BND, 2> m(P, src, dst, it.x0);
+        if constexpr (BND) {
+            const bool inner_x = m.per_x || (it.x0 >= 2 && it.x0 + 61 <= P.nx - 1);
+            const bool inner_y = m.per_y || (it.j0 >= 2 && it.j1 <= P.ny - 2);
+            if (inner_x && inner_y) m.run2(it.j0, it.j1);
+            else m.run2b(it.j0, it.j1);
+        } else {
+            m.run2(it.j0, it.j1);
+        }
+    }
+}
+
 }  // namespace lbfv

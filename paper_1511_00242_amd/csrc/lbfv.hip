@@ -104,8 +104,10 @@ struct lbfv_batch {
     BatchItem *d_items = nullptr;
     int nitems = 0, rows = 8, gsteps = 100;      // rows: from a sweep on the 96-case batch
     int parity = 0;                  // all cases share the step parity
+    int tblock = 1;                  // time steps per launch (1 or 2; 2: 60-column strips)
+    bool wave_per_item = false;      // grid of one wave per work item instead of the resident waves
     bool bnd = false;                // some case has a non-periodic side
-    int slots[2] = {0, 0};           // resident waves of the batch kernel, per scheme
+    int slots[2][2] = {{0, 0}, {0, 0}};   // resident waves of the batch kernels, per time block and scheme
     hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     bool has_state = false;
     std::string last_error;
@@ -318,20 +320,24 @@ void *step_fn_variant(int variant, int scheme, bool bnd) {
     }
 }
 template <typename T, typename S, bool BND>
-void *batch_fn_b(int scheme) {
+void *batch_fn_b(int scheme, bool two) {
+    if (two)
+        return scheme == SCHEME_DUGKS ? (void *)batch2_kernel<T, S, SCHEME_DUGKS, BND>
+                                      : (void *)batch2_kernel<T, S, SCHEME_BKG, BND>;
     return scheme == SCHEME_DUGKS ? (void *)batch_kernel<T, S, SCHEME_DUGKS, BND>
                                   : (void *)batch_kernel<T, S, SCHEME_BKG, BND>;
 }
 template <typename T, typename S>
-void *batch_fn(int scheme, bool bnd) {
-    return bnd ? batch_fn_b<T, S, true>(scheme) : batch_fn_b<T, S, false>(scheme);
+void *batch_fn(int scheme, bool bnd, bool two) {
+    return bnd ? batch_fn_b<T, S, true>(scheme, two) : batch_fn_b<T, S, false>(scheme, two);
 }
-void *batch_fn_variant(int variant, int scheme, bool bnd) {
+// two: two time steps per launch (the cases in the 60-column strip layout)
+void *batch_fn_variant(int variant, int scheme, bool bnd, bool two) {
     switch (variant) {
-    case V_F64: return batch_fn<double, double>(scheme, bnd);
-    case V_F32: return batch_fn<float, float>(scheme, bnd);
-    case V_BF16: return batch_fn<float, __bf16>(scheme, bnd);
-    default: return batch_fn<float, _Float16>(scheme, bnd);
+    case V_F64: return batch_fn<double, double>(scheme, bnd, two);
+    case V_F32: return batch_fn<float, float>(scheme, bnd, two);
+    case V_BF16: return batch_fn<float, __bf16>(scheme, bnd, two);
+    default: return batch_fn<float, _Float16>(scheme, bnd, two);
     }
 }
 
@@ -659,6 +665,26 @@ int start_check(lbfv_ctx *c) {
     c->check_pending = true;
     c->steps_at_check = c->steps;
     return LBFV_OK;
+}
+
+// Copy the state in buf[from] into buf[from ^ 1] in the layout of strip width w (the
+// case's own strip and pitch still describe the source).
+hipError_t relayout(const HostCase &h, int from, int w, hipStream_t stream) {
+    const int64_t n = (int64_t)h.nx * h.ny;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    const int64_t pitch_d = padded_pitch(h.nx, w);
+    const void *src = h.buf[from];
+    void *dst = h.buf[from ^ 1];
+    if (h.esize == 8)
+        hipLaunchKernelGGL(relayout_kernel<uint64_t>, dim3(blocks), dim3(256), 0, stream, (const uint64_t *)src,
+                           (uint64_t *)dst, h.nx, h.ny, h.pitch, h.strip, pitch_d, w);
+    else if (h.esize == 4)
+        hipLaunchKernelGGL(relayout_kernel<uint32_t>, dim3(blocks), dim3(256), 0, stream, (const uint32_t *)src,
+                           (uint32_t *)dst, h.nx, h.ny, h.pitch, h.strip, pitch_d, w);
+    else
+        hipLaunchKernelGGL(relayout_kernel<uint16_t>, dim3(blocks), dim3(256), 0, stream, (const uint16_t *)src,
+                           (uint16_t *)dst, h.nx, h.ny, h.pitch, h.strip, pitch_d, w);
+    return hipGetLastError();
 }
 
 // a symmetry side (or the symmetry part of a side ending in a wall segment) needs the
@@ -1110,20 +1136,7 @@ int lbfv_set_time_block(lbfv_ctx *c, int32_t steps) {
             // move the current state into the other buffer in the new layout
             int st = poll_check(c, true);
             if (st) return st;
-            const int64_t n = (int64_t)h.nx * h.ny;
-            const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
-            const int64_t pitch_d = padded_pitch(h.nx, w);
-            void *src = h.buf[h.cur], *dst = h.buf[h.cur ^ 1];
-            if (h.esize == 8)
-                hipLaunchKernelGGL(relayout_kernel<uint64_t>, dim3(blocks), dim3(256), 0, c->stream,
-                                   (const uint64_t *)src, (uint64_t *)dst, h.nx, h.ny, h.pitch, h.strip, pitch_d, w);
-            else if (h.esize == 4)
-                hipLaunchKernelGGL(relayout_kernel<uint32_t>, dim3(blocks), dim3(256), 0, c->stream,
-                                   (const uint32_t *)src, (uint32_t *)dst, h.nx, h.ny, h.pitch, h.strip, pitch_d, w);
-            else
-                hipLaunchKernelGGL(relayout_kernel<uint16_t>, dim3(blocks), dim3(256), 0, c->stream,
-                                   (const uint16_t *)src, (uint16_t *)dst, h.nx, h.ny, h.pitch, h.strip, pitch_d, w);
-            HIPCHK(hipGetLastError());
+            HIPCHK(relayout(h, h.cur, w, c->stream));
             h.cur ^= 1;
         }
         h.set_strip(w);
@@ -1424,27 +1437,55 @@ struct BatchArgs {
     }
 };
 
-// Persistent grid: exactly the blocks of 4 waves that fit on the device at once (from
-// the kernel's occupancy), capped by the work list.
-int batch_grid(lbfv_batch *b, int scheme) {
-    int &slots = b->slots[scheme];
+// resident waves of the batch kernel (from its occupancy)
+int batch_slots(lbfv_batch *b, int scheme, bool two) {
+    int &slots = b->slots[two ? 1 : 0][scheme];
     if (slots <= 0) {
-        slots = resident_waves(batch_fn_variant(b->variant, scheme, b->bnd), 4);
+        slots = resident_waves(batch_fn_variant(b->variant, scheme, b->bnd, two), 4);
         if (slots <= 0) slots = 256 * 8;
     }
-    return std::max(1, std::min((b->nitems + 3) / 4, slots / 4));
+    return slots;
 }
 
-int batch_launch_one(lbfv_batch *b, int scheme, int parity) {
+// Persistent grid: exactly the blocks of 4 waves that fit on the device at once, capped
+// by the work list; or one wave per item, so that the hardware hands a freed slot the next
+// block (items of uneven cost then balance themselves).
+int batch_grid(lbfv_batch *b, int scheme, bool two) {
+    const int all = std::max(1, (b->nitems + 3) / 4);
+    if (b->wave_per_item) return all;
+    return std::min(all, batch_slots(b, scheme, two) / 4);
+}
+
+// Row-block heights in 2 ... 64 that a cost model ranks best for the batch: whole rounds
+// of the resident waves times the rows each item marches (its rows plus the rows the
+// stencil reads around them at each step level); returns up to `count` heights.
+std::vector<int> batch_balanced_rows(const lbfv_batch *b, int slots, int count) {
+    std::vector<std::pair<double, int>> cost;
+    for (int r = 2; r <= 64; ++r) {
+        int64_t n = 0;
+        for (const auto &h : b->cases) n += (int64_t)((h.nx + h.strip - 1) / h.strip) * ((h.ny + r - 1) / r);
+        const int64_t rounds = (n + slots - 1) / slots;
+        cost.push_back({(double)rounds * (r + 2 * b->tblock), r});
+    }
+    std::stable_sort(cost.begin(), cost.end());
+    std::vector<int> out;
+    for (int i = 0; i < count && i < (int)cost.size(); ++i) out.push_back(cost[i].second);
+    return out;
+}
+
+// one launch: one time step, or two when two is set (the cases then hold 60-column strips)
+int batch_launch_one(lbfv_batch *b, int scheme, int parity, bool two = false) {
     BatchArgs a{b->d_params, b->d_items, b->nitems, parity};
     a.bind();
-    hipError_t e = hipLaunchKernel(batch_fn_variant(b->variant, scheme, b->bnd), dim3(batch_grid(b, scheme)), dim3(256), a.args, 0,
-                                   b->stream);
+    hipError_t e = hipLaunchKernel(batch_fn_variant(b->variant, scheme, b->bnd, two), dim3(batch_grid(b, scheme, two)),
+                                   dim3(256), a.args, 0, b->stream);
     if (e != hipSuccess) return b->fail(LBFV_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
     return LBFV_OK;
 }
 
+// a graph of gsteps launches of the current time block
 int batch_build_graph(lbfv_batch *b, int scheme, int parity0) {
+    const bool two = b->tblock == 2;
     hipGraph_t g;
     if (hipGraphCreate(&g, 0) != hipSuccess) return b->fail(LBFV_EHIP, "hipGraphCreate failed");
     hipGraphNode_t prev = nullptr;
@@ -1453,8 +1494,8 @@ int batch_build_graph(lbfv_batch *b, int scheme, int parity0) {
         a.bind();
         hipKernelNodeParams kp;
         memset(&kp, 0, sizeof(kp));
-        kp.func = batch_fn_variant(b->variant, scheme, b->bnd);
-        kp.gridDim = dim3(batch_grid(b, scheme));
+        kp.func = batch_fn_variant(b->variant, scheme, b->bnd, two);
+        kp.gridDim = dim3(batch_grid(b, scheme, two));
         kp.blockDim = dim3(256);
         kp.kernelParams = a.args;
         hipGraphNode_t node;
@@ -1598,6 +1639,49 @@ int lbfv_batch_get_shape(const lbfv_batch *b, int32_t *graph_steps, int32_t *row
     return LBFV_OK;
 }
 
+int lbfv_batch_set_grid_form(lbfv_batch *b, int32_t wave_per_item) {
+    if (!b) return LBFV_EINVAL;
+    if (wave_per_item != 0 && wave_per_item != 1) return b->fail(LBFV_EINVAL, "lbfv_batch_set_grid_form: 0 or 1");
+    if ((bool)wave_per_item != b->wave_per_item) {
+        b->wave_per_item = wave_per_item;
+        batch_drop_graphs(b);
+    }
+    return LBFV_OK;
+}
+
+int lbfv_batch_get_grid_form(const lbfv_batch *b, int32_t *wave_per_item) {
+    if (!b || !wave_per_item) return LBFV_EINVAL;
+    *wave_per_item = b->wave_per_item ? 1 : 0;
+    return LBFV_OK;
+}
+
+int lbfv_batch_set_time_block(lbfv_batch *b, int32_t steps) {
+    if (!b) return LBFV_EINVAL;
+    if (steps != 1 && steps != 2) return b->fail(LBFV_EINVAL, "lbfv_batch_set_time_block: steps must be 1 or 2");
+    if (steps == b->tblock) return LBFV_OK;
+    // launches in flight read the case table that is rewritten below
+    hipError_t es = hipStreamSynchronize(b->stream);
+    if (es != hipSuccess) return b->fail(LBFV_EHIP, std::string("batch: ") + hipGetErrorString(es));
+    // every case moves its current state into the other buffer in the new strip layout
+    const int w = steps == 2 ? STRIP2 : STRIP1;
+    for (auto &h : b->cases) {
+        hipError_t e = relayout(h, b->parity, w, b->stream);
+        if (e != hipSuccess) return b->fail(LBFV_EHIP, std::string("batch relayout: ") + hipGetErrorString(e));
+        h.set_strip(w);
+    }
+    b->parity ^= 1;
+    b->tblock = steps;
+    int st = is_f64(b->variant) ? batch_upload_params<double>(b) : batch_upload_params<float>(b);
+    if (!st) st = batch_build_items(b);
+    return st;
+}
+
+int lbfv_batch_get_time_block(const lbfv_batch *b, int32_t *steps) {
+    if (!b || !steps) return LBFV_EINVAL;
+    *steps = b->tblock;
+    return LBFV_OK;
+}
+
 int lbfv_batch_autotune(lbfv_batch *b, int scheme, int32_t trial_steps, double *best_ms) {
     if (!b) return LBFV_EINVAL;
     if (scheme != LBFV_DUGKS && scheme != LBFV_BKG) return b->fail(LBFV_EINVAL, "unknown scheme");
@@ -1610,7 +1694,8 @@ int lbfv_batch_autotune(lbfv_batch *b, int scheme, int32_t trial_steps, double *
         (void)hipGetLastError();
         return b->fail(LBFV_ENOMEM, "batch autotune: cannot allocate the state copy");
     }
-    const int parity0 = b->parity, rows0 = b->rows, gsteps0 = b->gsteps;
+    const int parity0 = b->parity, rows0 = b->rows, gsteps0 = b->gsteps, tb0 = b->tblock;
+    const bool wpi0 = b->wave_per_item;
     hipError_t e = hipSuccess;
     size_t off = 0;
     for (const auto &h : b->cases) {
@@ -1622,36 +1707,54 @@ int lbfv_batch_autotune(lbfv_batch *b, int scheme, int32_t trial_steps, double *
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     int st = e == hipSuccess ? LBFV_OK : b->fail(LBFV_EHIP, std::string("batch autotune: ") + hipGetErrorString(e));
-    // candidate row-block heights; each is timed as one replay of a graph of ts steps after
-    // a first replay that builds and warms it (ts even, so both replays use one graph)
+    // candidates: time blocks 1 and 2, times row-block heights (powers of two and the cost
+    // model's best), times the two grid forms; each is timed as one replay of a graph of ts
+    // launches after a first replay that builds and warms it (ts even, so both replays use
+    // one graph); the trials advance the state, which is put back below
     const int ts = trial_steps + (trial_steps & 1);
-    int best_rows = rows0;
+    int best_rows = rows0, best_tb = tb0;
+    bool best_wpi = wpi0;
     double best = INFINITY;
     b->gsteps = ts;
-    for (int r : {2, 4, 8, 16, 32, 64}) {
-        if (st) break;
-        b->rows = r;
-        if ((st = batch_build_items(b))) break;
-        if ((st = lbfv_batch_step(b, scheme, ts))) break;
-        float t = 0;
-        e = hipEventRecord(e0, b->stream);
-        if (e == hipSuccess && (st = lbfv_batch_step(b, scheme, ts))) break;
-        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
-        if (e != hipSuccess) {
-            st = b->fail(LBFV_EHIP, std::string("batch autotune timing: ") + hipGetErrorString(e));
-            break;
-        }
-        if (t / ts < best) {
-            best = t / ts;
-            best_rows = r;
+    for (int tb : {1, 2}) {
+        if (st || (st = lbfv_batch_set_time_block(b, tb))) break;
+        std::vector<int> heights = {2, 4, 8, 16, 32, 64};
+        for (int r : batch_balanced_rows(b, batch_slots(b, scheme, tb == 2), 3))
+            if (std::find(heights.begin(), heights.end(), r) == heights.end()) heights.push_back(r);
+        for (int trial = 0; trial < 2 * (int)heights.size() && !st; ++trial) {
+            const int r = heights[trial >> 1];
+            b->wave_per_item = trial & 1;
+            b->rows = r;
+            if ((st = batch_build_items(b))) break;
+            if ((st = lbfv_batch_step(b, scheme, tb * ts))) break;
+            float t = 0;
+            e = hipEventRecord(e0, b->stream);
+            if (e == hipSuccess && (st = lbfv_batch_step(b, scheme, tb * ts))) break;
+            if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+            if (e != hipSuccess) {
+                st = b->fail(LBFV_EHIP, std::string("batch autotune timing: ") + hipGetErrorString(e));
+                break;
+            }
+            if (t / (tb * ts) < best) {
+                best = t / (tb * ts);
+                best_rows = r;
+                best_tb = tb;
+                best_wpi = b->wave_per_item;
+            }
         }
     }
-    // restore the state, the parity and the graph length; keep the fastest height
+    // restore the layout, the state, the parity and the graph length (the saved state is
+    // in the layout of the entry time block); keep the fastest shape
+    (void)hipStreamSynchronize(b->stream);
     b->gsteps = gsteps0;
+    b->tblock = tb0;
+    b->wave_per_item = st ? wpi0 : best_wpi;
+    for (auto &h : b->cases) h.set_strip(tb0 == 2 ? STRIP2 : STRIP1);
     b->rows = st ? rows0 : best_rows;
-    int st2 = batch_build_items(b);
+    int st2 = is_f64(b->variant) ? batch_upload_params<double>(b) : batch_upload_params<float>(b);
+    if (!st2) st2 = batch_build_items(b);
     off = 0;
     hipError_t re = hipSuccess;
     for (const auto &h : b->cases) {
@@ -1667,6 +1770,7 @@ int lbfv_batch_autotune(lbfv_batch *b, int scheme, int32_t trial_steps, double *
     if (st) return st;
     if (st2) return st2;
     if (re != hipSuccess) return b->fail(LBFV_EHIP, std::string("batch autotune restore: ") + hipGetErrorString(re));
+    if ((st = lbfv_batch_set_time_block(b, best_tb))) return st;
     if (best_ms) *best_ms = best;
     return LBFV_OK;
 }
@@ -1800,7 +1904,11 @@ int lbfv_batch_step(lbfv_batch *b, int scheme, int32_t n) {
     if (!b) return LBFV_EINVAL;
     if (scheme != LBFV_DUGKS && scheme != LBFV_BKG) return b->fail(LBFV_EINVAL, "unknown scheme");
     if (n < 0) return b->fail(LBFV_EINVAL, "nsteps must be >= 0");
-    while (n >= b->gsteps) {
+    // with a time block of 2 every launch advances two steps; an odd last step is a
+    // one-step launch on the same layout
+    const bool two = b->tblock == 2;
+    const int per = two ? 2 : 1;
+    while (n >= per * b->gsteps) {
         hipGraphExec_t &g = b->gexec[scheme][b->parity];
         if (!g) {
             int st = batch_build_graph(b, scheme, b->parity);
@@ -1809,9 +1917,14 @@ int lbfv_batch_step(lbfv_batch *b, int scheme, int32_t n) {
         hipError_t e = hipGraphLaunch(g, b->stream);
         if (e != hipSuccess) return b->fail(LBFV_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
         b->parity ^= (b->gsteps & 1);
-        n -= b->gsteps;
+        n -= per * b->gsteps;
     }
-    for (; n > 0; --n) {
+    for (; n >= per; n -= per) {
+        int st = batch_launch_one(b, scheme, b->parity, two);
+        if (st) return st;
+        b->parity ^= 1;
+    }
+    if (n > 0) {
         int st = batch_launch_one(b, scheme, b->parity);
         if (st) return st;
         b->parity ^= 1;

@@ -40,6 +40,8 @@ EXPORTS = (
     "lbfv_batch_init_equilibrium", "lbfv_batch_set_f", "lbfv_batch_get_f", "lbfv_batch_step",
     "lbfv_batch_moments", "lbfv_batch_nonfinite", "lbfv_batch_set_shape", "lbfv_batch_info",
     "lbfv_batch_get_shape", "lbfv_batch_autotune", "lbfv_batch_last_error",
+    "lbfv_batch_set_time_block", "lbfv_batch_get_time_block", "lbfv_batch_set_grid_form",
+    "lbfv_batch_get_grid_form",
     "lbfv_batch_destroy",
 )
 
@@ -128,6 +130,10 @@ def lib():
             "lbfv_batch_set_shape": ([vp, C.c_int32, C.c_int32], ip),
             "lbfv_batch_get_shape": ([vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], ip),
             "lbfv_batch_autotune": ([vp, ip, C.c_int32, dp], ip),
+            "lbfv_batch_set_time_block": ([vp, C.c_int32], ip),
+            "lbfv_batch_get_time_block": ([vp, C.POINTER(C.c_int32)], ip),
+            "lbfv_batch_set_grid_form": ([vp, C.c_int32], ip),
+            "lbfv_batch_get_grid_form": ([vp, C.POINTER(C.c_int32)], ip),
             "lbfv_batch_info": ([vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)], ip),
             "lbfv_batch_destroy": ([vp], ip),
         }
@@ -421,8 +427,27 @@ class Batch:
         _check(lib().lbfv_batch_get_shape(self.h, C.byref(k), C.byref(r)), self.h, batch=True)
         return k.value, r.value
 
+    def set_time_block(self, steps: int):
+        """Time steps per launch of every case (1 or 2); results are bit-identical."""
+        _check(lib().lbfv_batch_set_time_block(self.h, int(steps)), self.h, batch=True)
+
+    def get_time_block(self) -> int:
+        t = C.c_int32()
+        _check(lib().lbfv_batch_get_time_block(self.h, C.byref(t)), self.h, batch=True)
+        return t.value
+
+    def set_grid_form(self, wave_per_item: bool):
+        """False: the resident waves walk the work list; True: one wave per work item."""
+        _check(lib().lbfv_batch_set_grid_form(self.h, int(bool(wave_per_item))), self.h, batch=True)
+
+    def get_grid_form(self) -> bool:
+        t = C.c_int32()
+        _check(lib().lbfv_batch_get_grid_form(self.h, C.byref(t)), self.h, batch=True)
+        return bool(t.value)
+
     def autotune(self, scheme: int, trial_steps: int = 20) -> float:
-        """Pick the work list's row-block height by timing; the state is left unchanged."""
+        """Pick the time block and the work list's row-block height by timing; the state is
+        left unchanged."""
         ms = C.c_double()
         _check(lib().lbfv_batch_autotune(self.h, int(scheme), int(trial_steps), C.byref(ms)), self.h, batch=True)
         return ms.value

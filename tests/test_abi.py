@@ -70,6 +70,10 @@ def test_null_pointers_are_rejected():
     assert lib.lbfv_batch_nonfinite(None, None) == L.LBFV_EINVAL
     assert lib.lbfv_batch_autotune(None, 0, 10, None) == L.LBFV_EINVAL
     assert lib.lbfv_batch_get_shape(None, None, None) == L.LBFV_EINVAL
+    assert lib.lbfv_batch_set_time_block(None, 2) == L.LBFV_EINVAL
+    assert lib.lbfv_batch_get_time_block(None, None) == L.LBFV_EINVAL
+    assert lib.lbfv_batch_set_grid_form(None, 1) == L.LBFV_EINVAL
+    assert lib.lbfv_batch_get_grid_form(None, None) == L.LBFV_EINVAL
     assert lib.lbfv_batch_last_error(None) is not None
 
 

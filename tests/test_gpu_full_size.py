@@ -10,8 +10,8 @@
   which is wrong only inside the margin) and their centres are compared cell by cell
   with the GPU's full-size run: strip seams, the ragged last strip, row-block seams
   and the periodic corner.
-- The 96-case batch (one 100-step graph replay) with a sample of cases of every size
-  and both families against the oracle.
+- The 96-case batch (one 100-step graph replay, one and two steps per launch) with a
+  sample of cases of every size and both families against the oracle.
 Bars: FP64 relative L2 <= 1e-12 on f~ and on u; FP32 deviation storage <= 1e-5 on u.
 Where the FP64 oracle's own rounding has grown past 1e-13 (its distance from the
 extended-precision build of the same oracle, recorded in the fixture), the FP64 bar
@@ -239,9 +239,12 @@ def test_tg4096_2000_steps_physics_and_precisions():
 SAMPLE_CASES = [0, 2, 1, 4, 49, 52, 55, 48]     # TG 64/128/256/512, cavity 64/128/256/512
 
 
-@pytest.mark.parametrize("compute,storage", [(L.LBFV_FP64, L.LBFV_STORE_NATIVE),
-                                             (L.LBFV_FP32, L.LBFV_STORE_DEV_FP32)])
-def test_batch96_sampled_cases(compute, storage):
+@pytest.mark.parametrize("compute,storage,tb", [(L.LBFV_FP64, L.LBFV_STORE_NATIVE, 1),
+                                                (L.LBFV_FP32, L.LBFV_STORE_DEV_FP32, 1),
+                                                (L.LBFV_FP32, L.LBFV_STORE_DEV_FP32, 2),
+                                                (L.LBFV_FP32, L.LBFV_STORE_DEV_FP32, "tuned")])
+def test_batch96_sampled_cases(compute, storage, tb):
+    """tb "tuned": the launch shape the benchmark times, chosen by the batch autotuner."""
     cases = I.batch_cases(96, seed=1511)
     sides = {cases[i].xf.size - 1 for i in SAMPLE_CASES}
     assert sides == {64, 128, 256, 512}
@@ -253,7 +256,14 @@ def test_batch96_sampled_cases(compute, storage):
         b.set_f(i, f0)
         if i in SAMPLE_CASES:
             f0s[i] = f0
-    b.step(L.LBFV_DUGKS, 100)                   # one replay of the 100-step graph
+    if tb == "tuned":
+        b.autotune(L.LBFV_DUGKS, 20)
+        tb = b.get_time_block()
+        print(f"batch96 tuned: time block {tb}, shape {b.get_shape()}, {b.info()[1]} items", flush=True)
+    else:
+        b.set_time_block(tb)
+    b.set_shape(graph_steps=100 // tb)
+    b.step(L.LBFV_DUGKS, 100)                   # one replay of a 100-step graph
     for i in SAMPLE_CASES:
         w = cases[i]
         ora = O.Case(w.xf, w.yf, w.rt, w.tau, w.dt, w.bcs, threads=THREADS)
@@ -262,7 +272,7 @@ def test_batch96_sampled_cases(compute, storage):
         _, ur, vr = ora.moments(ref)
         _, ug, vg = ora.moments(g)
         eu = rel(np.stack([ug, vg]), np.stack([ur, vr]))
-        print(f"batch96 case {i} ({w.name}) compute={compute}: f {rel(g, ref):.2e} u {eu:.2e}", flush=True)
+        print(f"batch96 case {i} ({w.name}) compute={compute} tb={tb}: f {rel(g, ref):.2e} u {eu:.2e}", flush=True)
         if compute == L.LBFV_FP64:
             assert rel(g, ref) < TOL64 and eu < TOL64
         else:

@@ -323,7 +323,7 @@ def test_batch_matches_oracle_per_case(compute, storage, tol):
 
 def test_batch_autotune_keeps_state_and_errors_name_the_batch():
     """lbfv_batch_autotune: the state and step parity are unchanged by its trial steps,
-    the chosen height is one of its candidates, and stepping afterwards still matches
+    the chosen shape is one of its candidates, and stepping afterwards still matches
     the oracle (FP64).  A failing batch call reports the batch's own message."""
     cases = _small_batch()
     b = L.Batch(cases, compute=L.LBFV_FP64, storage=L.LBFV_STORE_NATIVE)
@@ -338,8 +338,9 @@ def test_batch_autotune_keeps_state_and_errors_name_the_batch():
     before = [b.get_f(i) for i in range(len(cases))]
     ms = b.autotune(L.LBFV_DUGKS, 7)
     k, rows = b.get_shape()
-    print(f"batch autotune: rows {rows}, {ms:.4f} ms/step, graph length {k}")
-    assert rows in (2, 4, 8, 16, 32, 64) and k == 10 and ms > 0
+    tb = b.get_time_block()
+    print(f"batch autotune: rows {rows}, time block {tb}, {ms:.4f} ms/step, graph length {k}")
+    assert 2 <= rows <= 64 and tb in (1, 2) and k == 10 and ms > 0
     for i in range(len(cases)):
         assert np.array_equal(b.get_f(i), before[i])
     b.step(L.LBFV_DUGKS, 10)
@@ -349,6 +350,59 @@ def test_batch_autotune_keeps_state_and_errors_name_the_batch():
         b.step(7, 1)
     assert "unknown scheme" in str(e.value)
     b.close()
+
+
+def _batch_sides_mix():
+    """the small batch plus a case per side set that the batched form takes (no wall
+    segments), on meshes of one, two and three 60-column strips"""
+    out = _small_batch()
+    for k, sides in enumerate(_side_sets(70)[:4]):
+        nx, ny = (45, 130, 70, 121)[k], (66, 19, 41, 7)[k]
+        w = _mixed_workload(nx, ny)
+        out.append(I.Workload(f"sides{k}", w.xf, w.yf, w.tau, w.dt, sides, w.rho, w.ux, w.uy))
+    return out
+
+
+@pytest.mark.parametrize("compute,storage", [(L.LBFV_FP64, L.LBFV_STORE_NATIVE),
+                                             (L.LBFV_FP32, L.LBFV_STORE_DEV_FP32),
+                                             (L.LBFV_FP32, L.LBFV_STORE_DEV_BF16)])
+@pytest.mark.parametrize("scheme", [L.LBFV_DUGKS, L.LBFV_BKG])
+def test_batch_two_steps_per_launch_equal_one(compute, storage, scheme):
+    """lbfv_batch_set_time_block(2): the same bits as one step per launch on every case,
+    through graph replays, two-step launches, an odd last step and switches of the time
+    block with a state in flight (each switch moves the state between strip layouts), with
+    the two grid forms.  With 16-bit storage the intermediate step of a two-step launch is not rounded to 16
+    bits: there both results are compared with the oracle instead."""
+    cases = _batch_sides_mix()
+    f0s = [perturbed_state(oracle_case(w, 1), w, 40 + i) for i, w in enumerate(cases)]
+    outs = []
+    for tb in (1, 2):
+        b = L.Batch(cases, compute=compute, storage=storage)
+        b.set_shape(graph_steps=4, rows=8)
+        b.set_grid_form(tb == 2)          # the two-step run also takes the other grid form
+        assert b.get_grid_form() == (tb == 2)
+        for i, f0 in enumerate(f0s):
+            b.set_f(i, f0)
+        b.step(scheme, 3)
+        b.set_time_block(tb)
+        assert b.get_time_block() == tb
+        b.step(scheme, 19)        # two replays of a 4-launch graph, one launch, one odd step
+        b.set_time_block(1)
+        b.step(scheme, 2)
+        b.set_time_block(tb)
+        b.step(scheme, 3)
+        outs.append([b.get_f(i) for i in range(len(cases))])
+        b.close()
+    for i, (a, c) in enumerate(zip(*outs)):
+        assert np.all(np.isfinite(a)), cases[i].name
+        if storage != L.LBFV_STORE_DEV_BF16:
+            assert np.array_equal(a, c), (cases[i].name, rel(c, a))
+            continue
+        ora = oracle_case(cases[i], 1)
+        ref = ora.run(f0s[i], O.DUGKS if scheme == L.LBFV_DUGKS else O.BKG, 27)
+        e1, e2 = u_rel(ora, a, ref), u_rel(ora, c, ref)
+        print(f"batch bf16 {cases[i].name}: u error {e1:.2e} (one step per launch), {e2:.2e} (two)")
+        assert e2 < 2 * e1 + 1e-6, cases[i].name
 
 
 # ------------------------------------------------------------------ full-size workload
