@@ -46,6 +46,8 @@ def parse():
     p.add_argument("--cpu-steps", type=int, default=12)
     p.add_argument("--only", default="", help="comma list of variant names to run")
     p.add_argument("--tile", default="", help="rows,waves_per_block for every run (skips the autotuner)")
+    p.add_argument("--batch-shape", default="",
+                   help="time_block,rows,wave_per_item (0/1) of the batch (skips its autotuner)")
     p.add_argument("--time-block", type=int, default=HEADLINE_TIME_BLOCK,
                    help="steps per launch with --tile on doubly periodic meshes (1 or 2)")
     p.add_argument("--copy-probe-mb", type=int, default=0,
@@ -123,7 +125,7 @@ def run_single(name, w, scheme, compute, storage, steps, warmup, check_every, st
     return out
 
 
-def run_batch(steps, warmup, stream):
+def run_batch(steps, warmup, stream, shape=""):
     import torch
     from paper_1511_00242_amd import inputs as I
     from paper_1511_00242_amd import lbfv as L
@@ -131,7 +133,13 @@ def run_batch(steps, warmup, stream):
     b = L.Batch(cases, stream=stream.cuda_stream)
     for i, w in enumerate(cases):
         b.init_equilibrium(i, w.rho, w.ux, w.uy)
-    b.autotune(L.LBFV_DUGKS, 20)              # time block and row-block height (state kept)
+    if shape:
+        tb, rows, per_item = (int(x) for x in shape.split(","))
+        b.set_time_block(tb)
+        b.set_shape(rows=rows)
+        b.set_grid_form(per_item)
+    else:
+        b.autotune(L.LBFV_DUGKS, 20)          # time block, row-block height, grid (state kept)
     graph_steps, rows = b.get_shape()
     tb = b.get_time_block()
     per_item = b.get_grid_form()
@@ -481,7 +489,7 @@ def main():
             print(f"[bench] {name}: {r['ms_per_step'] * 1e3:.2f} us/step {r['mlups']:.0f} MLUPS", file=sys.stderr,
                   flush=True)
         if not only or "batch" in only:
-            r = run_batch(200, 200, stream)
+            r = run_batch(200, 200, stream, a.batch_shape)
             variants["batch"] = r
             print(f"[bench] batch: {r['ms_per_step']:.4f} ms/step {r['mlups']:.0f} MLUPS", file=sys.stderr,
                   flush=True)
