@@ -204,9 +204,9 @@ const char *lbfv_batch_last_error(const lbfv_batch *b);   /* b NULL: last error 
 
 /* ------------------------------------------------------------------------------
  * Batched form: many independent cases of uneven size, Reynolds number and boundary
- * type advanced together.  One persistent kernel launch per time step walks a flat
- * list of (case, strip, row block) items; lbfv_batch_step replays a HIP graph of
- * K such launches.  Compute / storage follow opts (FP32 deviation storage is the
+ * type advanced together.  One kernel launch per time step (or per two, see
+ * lbfv_batch_set_time_block) covers a flat list of (case, strip, row block) items;
+ * lbfv_batch_step replays a HIP graph of K such launches.  Compute / storage follow opts (FP32 deviation storage is the
  * intended use).  bc_kind per side: 0 periodic, 1 wall (bc_val = uwx, uwy),
  * 2 inflow (rho, ux, uy), 3 outflow (order), 4 symmetry. */
 typedef struct {

@@ -1,6 +1,6 @@
 // batch_kernels.hpp -- gfx950 device code of the batched form: many independent
 // cases of uneven size, relaxation time, time step and boundary kinds advanced by one
-// persistent launch per time step, with the step kernel's per-wave march.
+// launch per time step (or per two), with the step kernels' per-wave marches.
 #pragma once
 #include "kernels.hpp"
 
@@ -11,8 +11,9 @@ struct BatchItem {
     int32_t c, x0, j0, j1;
 };
 
-// Batched persistent form: every wave walks the flat work list over all cases with a
-// grid stride; each case carries its own mesh, tau, dt, boundaries and buffers.
+// Batched form: every wave walks the flat work list over all cases with a grid stride
+// (a grid of one wave per item takes one item per wave); each case carries its own
+// mesh, tau, dt, boundaries and buffers.
 template <typename T, typename S, int SCHEME, bool BND>
 __global__ __launch_bounds__(256) void batch_kernel(const StepParams<T> *__restrict__ cases,
                                                     const BatchItem *__restrict__ items, int nitems,

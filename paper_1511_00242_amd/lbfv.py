@@ -352,7 +352,8 @@ class Context:
 
 
 class Batch:
-    """Many independent cases stepped by one persistent kernel per time step."""
+    """Many independent cases stepped together by one kernel launch per time step (or per
+    two steps)."""
 
     def __init__(self, workloads, *, rt=1.0 / 3.0, compute=LBFV_FP32, storage=LBFV_STORE_DEV_FP32,
                  rho0=1.0, stream=None):

@@ -343,6 +343,11 @@ def test_batch_autotune_keeps_state_and_errors_name_the_batch():
     assert 2 <= rows <= 64 and tb in (1, 2) and k == 10 and ms > 0
     for i in range(len(cases)):
         assert np.array_equal(b.get_f(i), before[i])
+    # again from the other time block (the saved state is then in the other strip layout)
+    b.set_time_block(3 - tb)
+    b.autotune(L.LBFV_DUGKS, 7)
+    for i in range(len(cases)):
+        assert np.array_equal(b.get_f(i), before[i])
     b.step(L.LBFV_DUGKS, 10)
     for i, (ora, ref) in enumerate(refs):
         assert rel(b.get_f(i), ref) < TOL64
