@@ -895,10 +895,12 @@ __global__ __launch_bounds__(256) void step2_kernel(StepParams<T> P, int parity,
     m.run2(j0, j1);
 }
 
-// Two time steps per launch on a mesh with a non-periodic side (60-column strip layout).
+// Two time steps per launch on a mesh with a non-periodic side (60-column strip layout),
+// parameters by value (DUGKS and the collision-free forms). Waves whose columns
+// x0-2 .. x0+61 and rows j0-2 .. j1+1 all lie inside the mesh (or wrap on a periodic axis)
+// need no ghost cells: they take the periodic march, whose rows rotate without copies.
 template <typename T, typename S, int SCHEME>
-__global__ __launch_bounds__(256) void step2b_kernel(StepParams<T> P, int parity, int rows, int nstrips,
-                                                     int nwork) {
+__global__ __launch_bounds__(256) void step2b_kernel(StepParams<T> P, int parity, int rows, int nstrips, int nwork) {
     const int rb = xcd_block();
     const int wpb = blockDim.x >> 6;
     const int w = __builtin_amdgcn_readfirstlane(rb * wpb + (int)(threadIdx.x >> 6));
@@ -909,9 +911,32 @@ __global__ __launch_bounds__(256) void step2b_kernel(StepParams<T> P, int parity
     S *dst = (S *)P.buf[parity ^ 1];
     const int x0 = P.strip * sx;
     March<T, S, SCHEME, true, 2> m(P, src, dst, x0);
-    // waves whose columns x0-2 .. x0+61 and rows j0-2 .. j1+1 all lie inside the mesh (or
-    // wrap on a periodic axis) need no ghost cells: they take the periodic march, whose rows
-    // rotate without copies
+    const bool inner_x = m.per_x || (x0 >= 2 && x0 + 61 <= P.nx - 1);
+    const bool inner_y = m.per_y || (j0 >= 2 && j1 <= P.ny - 2);
+    if (inner_x && inner_y) m.run2(j0, j1);
+    else m.run2b(j0, j1);
+}
+
+// The same with the parameters read through a device pointer (BKG). By value they are held
+// in scalar registers across both inlined marches and spill; through a pointer the FP64 BKG
+// form needs no scratch and fits two waves per SIMD instead of one. The DUGKS form measured
+// faster by value. The body is repeated rather than shared through a device function: the
+// compiler allocates the two differently when called through one (more scratch by value,
+// scalar spills through the pointer).
+template <typename T, typename S, int SCHEME>
+__global__ __launch_bounds__(256) void step2b_ptr_kernel(const StepParams<T> *__restrict__ Pp, int parity, int rows,
+                                                         int nstrips, int nwork) {
+    const StepParams<T> &P = *Pp;
+    const int rb = xcd_block();
+    const int wpb = blockDim.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(rb * wpb + (int)(threadIdx.x >> 6));
+    if (w >= nwork) return;
+    const int sx = w % nstrips, sy = w / nstrips;
+    const int j0 = sy * rows, j1 = min(P.ny, j0 + rows);
+    const S *src = (const S *)P.buf[parity];
+    S *dst = (S *)P.buf[parity ^ 1];
+    const int x0 = P.strip * sx;
+    March<T, S, SCHEME, true, 2> m(P, src, dst, x0);
     const bool inner_x = m.per_x || (x0 >= 2 && x0 + 61 <= P.nx - 1);
     const bool inner_y = m.per_y || (j0 >= 2 && j1 <= P.ny - 2);
     if (inner_x && inner_y) m.run2(j0, j1);

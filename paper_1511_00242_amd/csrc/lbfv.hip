@@ -86,6 +86,12 @@ struct lbfv_ctx {
     bool check_pending = false;
     hipEvent_t check_event = nullptr;
     bool uprev_valid = false;
+    // parameters of the two-step BKG kernel with sides, one slot per scheme: device copy, pinned
+    // staging copy, the bytes last uploaded and the event of that upload
+    void *d_p2b = nullptr, *h_p2b = nullptr;
+    hipEvent_t p2b_event[4] = {};
+    bool p2b_pending[4] = {};
+    std::vector<char> p2b_last[4];
     std::string last_error;
 
     int fail(int status, const std::string &msg) {
@@ -298,7 +304,8 @@ void *step_fn(int scheme, bool bnd) {
 template <typename T, typename S>
 void *step2_fn(int scheme, bool bnd) {
     if (bnd)
-        return scheme == SCHEME_BKG ? (void *)step2b_kernel<T, S, SCHEME_BKG> : (void *)step2b_kernel<T, S, SCHEME_DUGKS>;
+        return scheme == SCHEME_BKG ? (void *)step2b_ptr_kernel<T, S, SCHEME_BKG>
+                                    : (void *)step2b_kernel<T, S, SCHEME_DUGKS>;
     return scheme == SCHEME_BKG ? (void *)step2_kernel<T, S, SCHEME_BKG> : (void *)step2_kernel<T, S, SCHEME_DUGKS>;
 }
 // two steps per launch; bnd: some side is not periodic
@@ -348,6 +355,7 @@ bool has_boundary(const HostCase &h) { return !(h.periodic_x() && h.periodic_y()
 struct StepArgs {
     StepParams<double> pd;
     StepParams<float> pf;
+    const void *pptr = nullptr;   // device copy of the parameters, for kernels that take a pointer
     int parity, rows, nstrips, nwork;
     void *args[5];
     void bind(bool f64) {
@@ -564,11 +572,71 @@ void *launch_fn(const HostCase &h, int scheme, bool two) {
     return two ? step2_fn_variant(h.variant, scheme, has_boundary(h)) : step_fn_variant(h.variant, scheme, has_boundary(h));
 }
 
+// Device copy of the parameters of the two-step BKG kernel with sides (which takes them
+// through a pointer; one slot per scheme, of which that kernel uses one).
+// A changed set is staged in pinned memory and copied on the context's stream, so launches
+// queued before the copy still read the previous set; the staging slot is rewritten only
+// after its previous copy has run.
+constexpr size_t P2B_SLOT = (sizeof(StepParams<double>) + 255) / 256 * 256;
+static_assert(sizeof(StepParams<float>) <= P2B_SLOT, "parameter slot too small");
+
+int p2b_upload(lbfv_ctx *c, int scheme, const void *p, size_t bytes, const void **dptr) {
+    if (!c->d_p2b) {
+        void *d = nullptr, *hs = nullptr;
+        if (hipMalloc(&d, 4 * P2B_SLOT) != hipSuccess || hipHostMalloc(&hs, 4 * P2B_SLOT, hipHostMallocDefault) != hipSuccess) {
+            if (d) (void)hipFree(d);
+            (void)hipGetLastError();
+            return c->fail(LBFV_ENOMEM, "cannot allocate the launch parameter copy");
+        }
+        for (auto &e : c->p2b_event)
+            if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+                (void)hipFree(d);
+                (void)hipHostFree(hs);
+                return c->fail(LBFV_EHIP, "hipEventCreate failed");
+            }
+        c->d_p2b = d;
+        c->h_p2b = hs;
+    }
+    char *d = (char *)c->d_p2b + scheme * P2B_SLOT, *hs = (char *)c->h_p2b + scheme * P2B_SLOT;
+    std::vector<char> &last = c->p2b_last[scheme];
+    if (last.size() != bytes || memcmp(last.data(), p, bytes) != 0) {
+        if (c->p2b_pending[scheme]) HIPCHK(hipEventSynchronize(c->p2b_event[scheme]));
+        memcpy(hs, p, bytes);
+        last.assign((const char *)p, (const char *)p + bytes);
+        HIPCHK(hipMemcpyAsync(d, hs, bytes, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipEventRecord(c->p2b_event[scheme], c->stream));
+        c->p2b_pending[scheme] = true;
+    }
+    *dptr = d;
+    return LBFV_OK;
+}
+
+// the arguments of a launch; the kernel that reads its parameters through a pointer (the
+// two-step BKG kernel with sides) gets the device copy
+int launch_args(lbfv_ctx *c, int scheme, int parity, const double ext[4], bool two, const StepShape &sh,
+                StepArgs &a) {
+    HostCase &h = c->hc;
+    fill_args(h, ext, sh, parity, scheme, a);
+    if (two && has_boundary(h) && scheme == SCHEME_BKG) {
+        const bool f64 = is_f64(h.variant);
+        int st = p2b_upload(c, scheme, f64 ? (const void *)&a.pd : (const void *)&a.pf, f64 ? sizeof(a.pd) : sizeof(a.pf),
+                            &a.pptr);
+        if (st) {
+            // a failed upload must not leave a stale record of what the device holds
+            c->p2b_last[scheme].clear();
+            return st;
+        }
+        a.args[0] = &a.pptr;
+    }
+    return LBFV_OK;
+}
+
 int launch_one(lbfv_ctx *c, int scheme, int parity, const double ext[4], bool two = false) {
     HostCase &h = c->hc;
     StepShape sh = step_shape(h, c->rows, c->wpb);
     StepArgs a;
-    fill_args(h, ext, sh, parity, scheme, a);
+    int st = launch_args(c, scheme, parity, ext, two, sh, a);
+    if (st) return st;
     HIPCHK(hipLaunchKernel(launch_fn(h, scheme, two), dim3(sh.nblocks), dim3(64 * sh.wpb), a.args, 0, c->stream));
     return LBFV_OK;
 }
@@ -581,7 +649,11 @@ int build_graph(lbfv_ctx *c, int scheme, int parity0, const double ext[4], bool 
     hipGraphNode_t prev = nullptr;
     for (int s = 0; s < c->gsteps; ++s) {
         StepArgs a;
-        fill_args(h, ext, sh, (parity0 + s) & 1, scheme, a);
+        int st = launch_args(c, scheme, (parity0 + s) & 1, ext, two, sh, a);
+        if (st) {
+            (void)hipGraphDestroy(g);
+            return st;
+        }
         hipKernelNodeParams kp;
         memset(&kp, 0, sizeof(kp));
         kp.func = launch_fn(h, scheme, two);
@@ -858,6 +930,10 @@ int lbfv_destroy(lbfv_ctx *c) {
     if (c->h_out) (void)hipHostFree(c->h_out);
     if (c->d_uprev) (void)hipFree(c->d_uprev);
     if (c->check_event) (void)hipEventDestroy(c->check_event);
+    if (c->d_p2b) (void)hipFree(c->d_p2b);
+    if (c->h_p2b) (void)hipHostFree(c->h_p2b);
+    for (auto e : c->p2b_event)
+        if (e) (void)hipEventDestroy(e);
     delete c;
     return LBFV_OK;
 }
