@@ -630,6 +630,33 @@ def test_two_steps_per_launch_with_sides_equal_two_launches(nx, ny):
                         assert rel(outs[1], ora.run(f0, oscheme, n)) < TOL64, (nx, ny, k, scheme)
 
 
+def test_two_step_bkg_parameter_copy_follows_side_changes():
+    """The two-step BKG kernel with sides reads its parameters from a device copy that is
+    refreshed only when they change: changing a wall velocity, a side kind and the scheme
+    between launches and graph replays gives the same bits as one step per launch."""
+    w = I.cavity(40, re=100.0, stretched=True)
+    ora = oracle_case(w, 1)
+    f0 = perturbed_state(ora, w, 23)
+    lid2 = [("wall", 0.0, 0.0), ("wall", 0.0, 0.0), ("wall", 0.0, 0.0), ("wall", 0.05, 0.0)]
+    open_e = [("wall", 0.0, 0.0), ("outflow", 1), ("wall", 0.0, 0.0), ("wall", 0.1, 0.0)]
+    outs = []
+    for tb in (1, 2):
+        with L.Context(w.xf, w.yf, w.tau, w.dt, bcs=w.bcs) as ctx:
+            ctx.set_f(f0)
+            ctx.set_time_block(tb)
+            ctx.bkg_step(70)          # graph replays of the default graph length, then launches
+            ctx.set_sides(lid2)
+            ctx.bkg_step(9)
+            ctx.dugks_step(4)
+            ctx.set_sides(open_e)
+            ctx.bkg_step(66)
+            ctx.set_sides(w.bcs)
+            ctx.bkg_step(5)
+            outs.append(ctx.get_f())
+    assert np.all(np.isfinite(outs[0]))
+    assert np.array_equal(outs[0], outs[1]), rel(outs[1], outs[0])
+
+
 def test_time_block_switch_keeps_state_and_falls_back_off_periodic():
     w = _periodic_workload(130, 20, 5)
     ora = oracle_case(w)
