@@ -877,6 +877,27 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams<T> P, int parity, 
     m.run(j0, j1);
 }
 
+// The one-step kernel of a mesh with a non-periodic side, parameters read through a device
+// pointer (all but the FP64 forms on the DUGKS march): by value they are held in scalar
+// registers and spill, and the boundary code then costs a wave per SIMD (FP64 BKG: 255 + 16
+// registers and one wave by value, 194 and two through the pointer; FP32 DUGKS 181 -> 142,
+// three waves instead of two).
+template <typename T, typename S, int SCHEME>
+__global__ __launch_bounds__(256) void step_ptr_kernel(const StepParams<T> *__restrict__ Pp, int parity, int rows,
+                                                       int nstrips, int nwork) {
+    const StepParams<T> &P = *Pp;
+    const int rb = xcd_block();
+    const int wpb = blockDim.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(rb * wpb + (int)(threadIdx.x >> 6));
+    if (w >= nwork) return;
+    const int sx = w % nstrips, sy = w / nstrips;
+    const int j0 = sy * rows, j1 = min(P.ny, j0 + rows);
+    const S *src = (const S *)P.buf[parity];
+    S *dst = (S *)P.buf[parity ^ 1];
+    March<T, S, SCHEME, true> m(P, src, dst, P.strip * sx);
+    m.run(j0, j1);
+}
+
 // Two time steps per launch on a doubly periodic mesh (state in the 60-column strip
 // layout): each wave reads its strip once, keeps the intermediate step in registers and
 // stores the second; a launch reads buf[parity] and writes buf[1-parity].
@@ -896,7 +917,7 @@ __global__ __launch_bounds__(256) void step2_kernel(StepParams<T> P, int parity,
 }
 
 // Two time steps per launch on a mesh with a non-periodic side (60-column strip layout),
-// parameters by value (DUGKS and the collision-free forms). Waves whose columns
+// parameters by value (the FP64 forms on the DUGKS march). Waves whose columns
 // x0-2 .. x0+61 and rows j0-2 .. j1+1 all lie inside the mesh (or wrap on a periodic axis)
 // need no ghost cells: they take the periodic march, whose rows rotate without copies.
 template <typename T, typename S, int SCHEME>
@@ -917,10 +938,10 @@ __global__ __launch_bounds__(256) void step2b_kernel(StepParams<T> P, int parity
     else m.run2b(j0, j1);
 }
 
-// The same with the parameters read through a device pointer (BKG). By value they are held
-// in scalar registers across both inlined marches and spill; through a pointer the FP64 BKG
-// form needs no scratch and fits two waves per SIMD instead of one. The DUGKS form measured
-// faster by value. The body is repeated rather than shared through a device function: the
+// The same with the parameters read through a device pointer (BKG, and the FP32 forms). By
+// value they are held in scalar registers across both inlined marches and spill; through a
+// pointer the FP64 BKG form needs no scratch and fits two waves per SIMD instead of one. The
+// FP64 DUGKS form measured faster by value. The body is repeated rather than shared through a device function: the
 // compiler allocates the two differently when called through one (more scratch by value,
 // scalar spills through the pointer).
 template <typename T, typename S, int SCHEME>

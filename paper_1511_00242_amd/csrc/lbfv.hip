@@ -6,6 +6,7 @@
 #include "batch_kernels.hpp"
 
 #include <algorithm>
+#include <type_traits>
 #include <array>
 #include <cmath>
 #include <cstdio>
@@ -86,8 +87,8 @@ struct lbfv_ctx {
     bool check_pending = false;
     hipEvent_t check_event = nullptr;
     bool uprev_valid = false;
-    // parameters of the two-step BKG kernel with sides, one slot per scheme: device copy, pinned
-    // staging copy, the bytes last uploaded and the event of that upload
+    // parameters of the kernels that take them through a pointer, one slot per scheme:
+    // device copy, pinned staging copy, the bytes last uploaded and the event of that upload
     void *d_p2b = nullptr, *h_p2b = nullptr;
     hipEvent_t p2b_event[4] = {};
     bool p2b_pending[4] = {};
@@ -292,20 +293,31 @@ StepShape step_shape(const HostCase &h, int rows, int wpb) {
     return s;
 }
 
-template <typename T, typename S, bool BND>
-void *step_fn_b(int scheme) {
-    return scheme == SCHEME_BKG ? (void *)step_kernel<T, S, SCHEME_BKG, BND>
-                                : (void *)step_kernel<T, S, SCHEME_DUGKS, BND>;
+// Kernels of a mesh with a non-periodic side read their parameters through a device copy,
+// except the FP64 forms built on the DUGKS march (DUGKS, central, upwind), which measured
+// faster with them by value; doubly periodic meshes pass them by value.
+bool params_by_pointer(int variant, int scheme, bool bnd) {
+    return bnd && (variant != V_F64 || scheme == SCHEME_BKG);
 }
+
+// one step per launch
 template <typename T, typename S>
 void *step_fn(int scheme, bool bnd) {
-    return bnd ? step_fn_b<T, S, true>(scheme) : step_fn_b<T, S, false>(scheme);
+    if (bnd) {
+        if (scheme == SCHEME_BKG) return (void *)step_ptr_kernel<T, S, SCHEME_BKG>;
+        if constexpr (std::is_same<T, double>::value) return (void *)step_kernel<T, S, SCHEME_DUGKS, true>;
+        else return (void *)step_ptr_kernel<T, S, SCHEME_DUGKS>;
+    }
+    return scheme == SCHEME_BKG ? (void *)step_kernel<T, S, SCHEME_BKG, false>
+                                : (void *)step_kernel<T, S, SCHEME_DUGKS, false>;
 }
 template <typename T, typename S>
 void *step2_fn(int scheme, bool bnd) {
-    if (bnd)
-        return scheme == SCHEME_BKG ? (void *)step2b_ptr_kernel<T, S, SCHEME_BKG>
-                                    : (void *)step2b_kernel<T, S, SCHEME_DUGKS>;
+    if (bnd) {
+        if (scheme == SCHEME_BKG) return (void *)step2b_ptr_kernel<T, S, SCHEME_BKG>;
+        if constexpr (std::is_same<T, double>::value) return (void *)step2b_kernel<T, S, SCHEME_DUGKS>;
+        else return (void *)step2b_ptr_kernel<T, S, SCHEME_DUGKS>;
+    }
     return scheme == SCHEME_BKG ? (void *)step2_kernel<T, S, SCHEME_BKG> : (void *)step2_kernel<T, S, SCHEME_DUGKS>;
 }
 // two steps per launch; bnd: some side is not periodic
@@ -572,8 +584,8 @@ void *launch_fn(const HostCase &h, int scheme, bool two) {
     return two ? step2_fn_variant(h.variant, scheme, has_boundary(h)) : step_fn_variant(h.variant, scheme, has_boundary(h));
 }
 
-// Device copy of the parameters of the two-step BKG kernel with sides (which takes them
-// through a pointer; one slot per scheme, of which that kernel uses one).
+// Device copy of the launch parameters for the kernels that take them through a pointer
+// (params_by_pointer), one slot per scheme.
 // A changed set is staged in pinned memory and copied on the context's stream, so launches
 // queued before the copy still read the previous set; the staging slot is rewritten only
 // after its previous copy has run.
@@ -611,13 +623,13 @@ int p2b_upload(lbfv_ctx *c, int scheme, const void *p, size_t bytes, const void 
     return LBFV_OK;
 }
 
-// the arguments of a launch; the kernel that reads its parameters through a pointer (the
-// two-step BKG kernel with sides) gets the device copy
+// the arguments of a launch; the kernels that read their parameters through a pointer get
+// the device copy
 int launch_args(lbfv_ctx *c, int scheme, int parity, const double ext[4], bool two, const StepShape &sh,
                 StepArgs &a) {
     HostCase &h = c->hc;
     fill_args(h, ext, sh, parity, scheme, a);
-    if (two && has_boundary(h) && scheme == SCHEME_BKG) {
+    if (params_by_pointer(h.variant, scheme, has_boundary(h))) {
         const bool f64 = is_f64(h.variant);
         int st = p2b_upload(c, scheme, f64 ? (const void *)&a.pd : (const void *)&a.pf, f64 ? sizeof(a.pd) : sizeof(a.pf),
                             &a.pptr);
