@@ -630,10 +630,11 @@ def test_two_steps_per_launch_with_sides_equal_two_launches(nx, ny):
                         assert rel(outs[1], ora.run(f0, oscheme, n)) < TOL64, (nx, ny, k, scheme)
 
 
-def test_two_step_bkg_parameter_copy_follows_side_changes():
-    """The two-step BKG kernel with sides reads its parameters from a device copy that is
-    refreshed only when they change: changing a wall velocity, a side kind and the scheme
-    between launches and graph replays gives the same bits as one step per launch."""
+def test_bkg_parameter_copy_follows_side_changes():
+    """The BKG kernels with sides read their parameters from a device copy that is refreshed
+    only when they change: changing a wall velocity, a side kind and the scheme between
+    launches and graph replays gives the same bits with one and two steps per launch, and
+    the oracle's result."""
     w = I.cavity(40, re=100.0, stretched=True)
     ora = oracle_case(w, 1)
     f0 = perturbed_state(ora, w, 23)
@@ -655,6 +656,17 @@ def test_two_step_bkg_parameter_copy_follows_side_changes():
             outs.append(ctx.get_f())
     assert np.all(np.isfinite(outs[0]))
     assert np.array_equal(outs[0], outs[1]), rel(outs[1], outs[0])
+    # both time blocks read the copy (one-step kernels with sides do too): the oracle, run
+    # segment by segment with each segment's sides, pins the sequence itself
+    def seg(bcs, f, scheme, n):
+        wb = I.Workload("seg", w.xf, w.yf, w.tau, w.dt, bcs, w.rho, w.ux, w.uy)
+        return oracle_case(wb, 1).run(f, scheme, n)
+    f = seg(w.bcs, f0, O.BKG, 70)
+    f = seg(lid2, f, O.BKG, 9)
+    f = seg(lid2, f, O.DUGKS, 4)
+    f = seg(open_e, f, O.BKG, 66)
+    f = seg(w.bcs, f, O.BKG, 5)
+    assert rel(outs[1], f) < TOL64, rel(outs[1], f)
 
 
 def test_time_block_switch_keeps_state_and_falls_back_off_periodic():
