@@ -43,7 +43,12 @@ def parse():
     p.add_argument("--check-every", type=int, default=100)
     p.add_argument("--no-variants", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
-    p.add_argument("--cpu-steps", type=int, default=12)
+    p.add_argument("--cpu-steps", type=int, default=6, help="oracle steps of the CPU baseline on all cores")
+    p.add_argument("--cpu-steps-one", type=int, default=2, help="oracle steps of the CPU baseline on one thread")
+    p.add_argument("--burn-in", type=float, default=0.5,
+                   help="seconds of GPU burn-in on the headline workload before its warm-up")
+    p.add_argument("--precision-steps", type=int, default=2000,
+                   help="steps after which the reduced-precision forms report their velocity error")
     p.add_argument("--only", default="", help="comma list of variant names to run")
     p.add_argument("--tile", default="", help="rows,waves_per_block for every run (skips the autotuner)")
     p.add_argument("--batch-shape", default="",
@@ -75,6 +80,36 @@ def parse():
     return p.parse_args()
 
 
+def burn_in(ctx, scheme, seconds, stream):
+    """Step the workload until `seconds` of wall time have passed (synchronised every few
+    steps), so that the timed region does not start on a GPU still clocking up after the
+    host-side setup.  Returns the wall time spent and the steps taken."""
+    import torch
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < seconds:
+        ctx.step(scheme, 8)
+        torch.cuda.synchronize()
+        n += 8
+    return time.perf_counter() - t0, n
+
+
+def trial_steps_for(ctx, scheme, stream, target_ms=20.0, cap=4000):
+    """Trial length of the autotuner: enough steps that one trial lasts about `target_ms`
+    at the current launch shape (short trials make the choice noisy)."""
+    import torch
+    ctx.step(scheme, 4)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ctx.step(scheme, 16)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    per = max(e0.elapsed_time(e1) / 16, 1e-4)
+    return int(min(cap, max(16, math.ceil(target_ms / per))))
+
+
 def timed_steps(ctx, scheme, steps, warmup, stream):
     """Warm up, then time `steps` steps with HIP events on the library's stream."""
     import torch
@@ -92,36 +127,42 @@ def timed_steps(ctx, scheme, steps, warmup, stream):
 
 
 def run_single(name, w, scheme, compute, storage, steps, warmup, check_every, stream, tile=None,
-               time_block=1, want_u=False):
+               time_block=1, burn_s=0.0):
     """Time `steps` steps of one workload; a fixed launch shape, or the autotuner's choice
     of shape and time block (one or two steps per launch).
-    want_u: also return the final velocity field (FP64 moments) under the key "u"."""
+    burn_s: wall time of GPU burn-in before the warm-up (the state is re-initialised after
+    it, so the timed steps start from the workload's initial state)."""
     from paper_1511_00242_amd import lbfv as L
     ctx = L.Context(w.xf, w.yf, w.tau, w.dt, rt=w.rt, bcs=w.bcs, compute=compute, storage=storage,
                     check_every=check_every, stream=stream.cuda_stream)
     ctx.bind_torch_buffers()
     ctx.init_equilibrium(w.rho, w.ux, w.uy)
+    tune = None
     if tile:
         ctx.set_time_block(time_block)
         ctx.set_tile(*tile)
     else:
-        # small meshes take microseconds per step: longer trials keep the choice out of the noise
-        ctx.autotune(scheme, 10 if w.nx * w.ny >= (1 << 20) else 200, os.environ.get("LBFV_TUNE_CACHE"))
+        trial = trial_steps_for(ctx, scheme, stream)
+        ctx.autotune(scheme, trial, os.environ.get("LBFV_TUNE_CACHE"))
+        tune = {"trial_steps": trial}
+    burn = None
+    if burn_s > 0:
+        sec, n = burn_in(ctx, scheme, burn_s, stream)
+        burn = {"seconds": round(sec, 3), "steps": n}
+        ctx.init_equilibrium(w.rho, w.ux, w.uy)
     ms, wall_ms = timed_steps(ctx, scheme, steps, warmup, stream)
     rows, wpb = ctx.get_tile()
     tb = ctx.get_time_block()
     tot = ctx.totals()                       # also re-checks for non-finite values
-    u = None
-    if want_u:
-        _, ux, uy = ctx.moments()
-        u = np.stack([ux, uy])
     ctx.close()
     cells = w.nx * w.ny
     per = ms / steps
     out = dict(name=name, ms_per_step=per, mlups=cells / (per * 1e-3) / 1e6, wall_ms=wall_ms,
                tile=[rows, wpb], time_block=tb, mass=tot[0])
-    if want_u:
-        out["u"] = u
+    if tune:
+        out["autotune"] = tune
+    if burn:
+        out["burn_in"] = burn
     return out
 
 
@@ -376,19 +417,110 @@ def profiled_traffic(tile, time_block, ms_per_step):
     return b / (time_block * ms_per_step * 1e-3) / 1e9, b
 
 
-def cpu_baseline(n, steps):
-    """The FP64 oracle on the host's cores over a bounded sample of the workload."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(n, steps_all, steps_one):
+    """The FP64 oracle as it stands, on the host's cores, over a bounded sample of the
+    workload: both schemes, on all the cores this process may use and on one thread.
+    `value` is DUGKS on all cores (the headline's scheme)."""
     from oracle import oracle as O
     from paper_1511_00242_amd import inputs as I
-    threads = min(16, os.cpu_count() or 1)
+    nproc = os.cpu_count() or 1
+    # the cores this process may use: its affinity mask, capped by OMP_NUM_THREADS where the
+    # host sets one (a shared host grants each job a share of its cores that way)
+    allowed = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else nproc
+    threads = max(1, min(allowed, int(os.environ.get("OMP_NUM_THREADS", allowed))))
     w = I.taylor_green(n)
-    c = O.Case(w.xf, w.yf, w.rt, w.tau, w.dt, w.bcs, threads=threads)
-    f = c.init_equilibrium(w.rho, w.ux, w.uy)
-    t0 = time.perf_counter()
-    c.run(f, O.DUGKS, steps)
-    el = time.perf_counter() - t0
-    return {"value": n * n * steps / el / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"taylor_green {n}x{n}, {steps} DUGKS steps, FP64 ({el:.1f} s)"}
+    legs = {}
+    total = 0.0
+    for sname, scheme in (("dugks", O.DUGKS), ("bkg", O.BKG)):
+        for th, steps in ((threads, steps_all), (1, steps_one)):
+            c = O.Case(w.xf, w.yf, w.rt, w.tau, w.dt, w.bcs, threads=th)
+            f = c.init_equilibrium(w.rho, w.ux, w.uy)
+            t0 = time.perf_counter()
+            c.run(f, scheme, steps)
+            el = time.perf_counter() - t0
+            total += el
+            legs[f"{sname}_{th}_threads"] = {"mlups": n * n * steps / el / 1e6, "threads": th, "steps": steps,
+                                             "seconds": round(el, 2)}
+            print(f"[bench] cpu oracle {sname} {th} threads: {n * n * steps / el / 1e6:.2f} MLUPS ({el:.1f} s)",
+                  file=sys.stderr, flush=True)
+    head = legs[f"dugks_{threads}_threads"]
+    return {"value": head["mlups"], "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": (f"taylor_green {n}x{n} FP64, DUGKS and BKG: {steps_all} steps on {threads} threads, "
+                       f"{steps_one} steps on 1 thread ({total:.1f} s in all)"),
+            "nproc": nproc, "affinity_cpus": allowed, "cpu_model": cpu_model(), "legs": legs}
+
+
+def read_oracle_fixture(path):
+    """(cells [(j, i)], f~ [9, n]) of a long-horizon fixture written by the oracle alone
+    (tests/golden/make_long_horizon.py); None if it is not there."""
+    if not os.path.exists(path):
+        return None
+    cells, vals = [], []
+    for line in open(path):
+        p = line.split()
+        if not p or p[0].startswith("#") or p[0] in ("steps", "totals", "ext"):
+            continue
+        cells.append((int(p[0]), int(p[1])))
+        vals.append([float(v) for v in p[2:]])
+    return cells, np.array(vals).T
+
+
+EX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=np.float64)   # D2Q9 unit directions, Sec. 2.1
+EY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=np.float64)
+
+
+def precision_errors(w, runs, stream, n=2000):
+    """The precision workload's accuracy at its parity point: every form advanced `n` steps
+    from the initial state at the launch shape its timing run used; u against the GPU FP64
+    run of the same scheme over every cell, and against the oracle at the cells of its
+    long-horizon fixture (c = 1 at RT = 1/3, so u = sum e f / sum f).  Returns
+    {name: {...}} for the reduced-precision forms."""
+    from paper_1511_00242_amd import lbfv as L
+    fields = {}
+    for name, sch, comp, sto, tile, tb in runs:
+        ctx = L.Context(w.xf, w.yf, w.tau, w.dt, rt=w.rt, bcs=w.bcs, compute=comp, storage=sto,
+                        check_every=0, stream=stream.cuda_stream)
+        ctx.init_equilibrium(w.rho, w.ux, w.uy)
+        ctx.set_time_block(tb)
+        ctx.set_tile(*tile)
+        ctx.step(sch, n)
+        _, ux, uy = ctx.moments()
+        ctx.close()
+        fields[name] = (sch, comp, np.stack([ux, uy]))
+    out = {}
+    for name, (sch, comp, u) in fields.items():
+        if comp == L.LBFV_FP64:
+            continue
+        ref = next(v[2] for v in fields.values() if v[0] == sch and v[1] == L.LBFV_FP64)
+        d = u - ref
+        e = {"steps": n, "u_rel_l2_vs_gpu_fp64": float(np.linalg.norm(d) / np.linalg.norm(ref)),
+             "u_max_vs_gpu_fp64": float(np.max(np.abs(d)) / np.max(np.abs(ref)))}
+        fx = read_oracle_fixture(os.path.join(ROOT, "tests", "golden",
+                                              f"long_tg{w.nx}_{'dugks' if sch == L.LBFV_DUGKS else 'bkg'}.txt"))
+        if fx is not None:
+            cells, f9 = fx
+            rho = f9.sum(axis=0)
+            uo = np.stack([EX @ f9 / rho, EY @ f9 / rho])
+            jj = np.array([c[0] for c in cells]); ii = np.array([c[1] for c in cells])
+            ug = u[:, jj, ii]
+            e["u_rel_l2_vs_oracle_sampled"] = float(np.linalg.norm(ug - uo) / np.linalg.norm(uo))
+            e["u_max_vs_oracle_sampled"] = float(np.max(np.abs(ug - uo)) / np.max(np.abs(uo)))
+            e["oracle_cells"] = len(cells)
+        out[name] = e
+        print(f"[bench] {name} after {n} steps: u vs GPU FP64 {e['u_rel_l2_vs_gpu_fp64']:.2e}"
+              + (f", vs oracle ({e['oracle_cells']} cells) {e['u_rel_l2_vs_oracle_sampled']:.2e}"
+                 if "oracle_cells" in e else ""), file=sys.stderr, flush=True)
+    return out
 
 
 def main():
@@ -427,11 +559,7 @@ def main():
     w = I.taylor_green(a.n)
     head = run_single("dugks_fp64", w, L.LBFV_DUGKS, L.LBFV_FP64, L.LBFV_STORE_NATIVE, steps, a.warmup,
                       a.check_every, stream, tile or HEADLINE_TILE, a.time_block if tile else HEADLINE_TIME_BLOCK,
-                      want_u=not a.no_variants)
-    # FP64 velocity fields after the same warm-up + timed steps, per scheme: the references
-    # of the reduced-precision variants' error (the FP64 GPU step is itself within 1e-12 of
-    # the oracle in the parity tests)
-    ref_u = {L.LBFV_DUGKS: head.pop("u", None)}
+                      burn_s=a.burn_in)
     print(f"[bench] dugks fp64 {a.n}^2: {head['ms_per_step']:.4f} ms/step {head['mlups']:.0f} MLUPS",
           file=sys.stderr, flush=True)
     # the roofline figure divides by the step kernel's own average duration: the same launches
@@ -453,14 +581,7 @@ def main():
         for name, sch, comp, sto, dt in specs:
             if only and name not in only:
                 continue
-            r = run_single(name, w, sch, comp, sto, steps, a.warmup, a.check_every, stream, tile, a.time_block,
-                           want_u=True)
-            u = r.pop("u")
-            if comp == L.LBFV_FP64:
-                ref_u[sch] = u
-            elif ref_u.get(sch) is not None:
-                ref = ref_u[sch]
-                r["u_rel_l2_vs_fp64"] = float(np.linalg.norm(u - ref) / np.linalg.norm(ref))
+            r = run_single(name, w, sch, comp, sto, steps, a.warmup, a.check_every, stream, tile, a.time_block)
             # bytes the method defines per step over the time per step; with two steps per
             # launch the state is read and written once per two steps, so this can pass the
             # HBM peak
@@ -472,19 +593,30 @@ def main():
             elif sch == L.LBFV_DUGKS:
                 r["speedup_vs_same_scheme_fp64"] = head["ms_per_step"] / r["ms_per_step"]
             variants[name] = r
-            err = f" u error vs FP64 {r['u_rel_l2_vs_fp64']:.2e}" if "u_rel_l2_vs_fp64" in r else ""
-            print(f"[bench] {name}: {r['ms_per_step']:.4f} ms/step {r['mlups']:.0f} MLUPS{err}", file=sys.stderr,
+            print(f"[bench] {name}: {r['ms_per_step']:.4f} ms/step {r['mlups']:.0f} MLUPS", file=sys.stderr,
                   flush=True)
+        # accuracy of the reduced-precision forms at the precision workload's parity point
+        if a.precision_steps > 0 and any(k in variants for k, *_ in specs[1:]):
+            runs = [("dugks_fp64", L.LBFV_DUGKS, L.LBFV_FP64, L.LBFV_STORE_NATIVE, head["tile"], head["time_block"])]
+            for name, sch, comp, sto, _ in specs:
+                if name in variants:
+                    runs.append((name, sch, comp, sto, variants[name]["tile"], variants[name]["time_block"]))
+            if "bkg_fp64" not in variants and "bkg_fp32dev" in variants:
+                runs.append(("bkg_fp64", L.LBFV_BKG, L.LBFV_FP64, L.LBFV_STORE_NATIVE, [0, 0], 1))
+            for name, e in precision_errors(w, runs, stream, a.precision_steps).items():
+                variants[name]["accuracy"] = e
         # the smaller workloads (L2 / Infinity-Cache resident, launch bound): MLUPS only
         small = [("tg32_dugks_fp64", I.taylor_green(32), L.LBFV_DUGKS),
                  ("cavity256_dugks_fp64", I.cavity(256), L.LBFV_DUGKS),
                  ("cavity256_bkg_fp64", I.cavity(256), L.LBFV_BKG),
-                 ("bl512x256_dugks_fp64", I.boundary_layer(), L.LBFV_DUGKS)]
+                 ("bl512x256_dugks_fp64", I.boundary_layer(), L.LBFV_DUGKS),
+                 ("bl512x256_bkg_fp64", I.boundary_layer(), L.LBFV_BKG)]
         for name, ws, sch in small:
             if only and name not in only:
                 continue
-            r = run_single(name, ws, sch, L.LBFV_FP64, L.LBFV_STORE_NATIVE, 10 * steps, a.warmup,
-                           a.check_every * 10, stream, tile, a.time_block)
+            # microseconds per step: at least 2000 timed steps (tens of milliseconds)
+            r = run_single(name, ws, sch, L.LBFV_FP64, L.LBFV_STORE_NATIVE, max(10 * steps, 2000),
+                           max(a.warmup, 200), a.check_every * 10, stream, tile, a.time_block)
             variants[name] = r
             print(f"[bench] {name}: {r['ms_per_step'] * 1e3:.2f} us/step {r['mlups']:.0f} MLUPS", file=sys.stderr,
                   flush=True)
@@ -522,12 +654,13 @@ def main():
                      "steps_per_launch": head["time_block"],
                      "kernel_ms": kern["ms_per_step"],
                      "bytes_per_cell_step": BYTES["f64"]},
+        "burn_in": head.get("burn_in"),
         "variants": variants,
         "context": {"paper_cpu_mlups_64x64": {"dugks": 2.08, "bkg": 3.90,
                                               "hardware": "Xeon E5-2670v3 (paper Sec. 3.1)"}},
     }
     if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(a.n, a.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(a.n, a.cpu_steps, a.cpu_steps_one)
     print(json.dumps(out), flush=True)
 
 

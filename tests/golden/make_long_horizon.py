@@ -1,24 +1,21 @@
 """Writes the long-horizon oracle fixtures ``long_<case>_<scheme>.txt``.
 
 Each fixture holds f~ (all nine directions) after many steps of the FP64 CPU
-oracle at a seeded sample of cells, plus the oracle's FP64 totals, for one of the
-full-size workloads:
+oracle at a seeded sample of cells, plus the oracle's FP64 totals, for a full-size
+workload whose whole field the oracle cannot advance within a test:
 
   tg4096   Taylor-Green 4096^2 on [0, 2 pi]^2 (u0 = 0.01, nu = 0.01, CFL 0.5),
-           2000 steps (t = 1.085)
-  cav256   lid-driven cavity 256^2, tanh mesh with largest adjacent ratio 1.05,
-           Re 1000, 20,000 steps from rest
-  bl512    boundary layer 512 x 256 (plate on the south side), 5,000 steps
+           2000 steps (t = 1.085), DUGKS and BKG
 
-The values are written by the oracle alone (nothing here touches the GPU
-library).  Run from the repository root:
+(The 256^2 cavity and the 512 x 256 boundary layer are compared over every cell at
+their parity points with the oracle run inside the test.)  The values are written by
+the oracle alone (nothing here touches the GPU library).  Run from the repository
+root:
 
-    python tests/golden/make_long_horizon.py cav256 dugks [threads] [--extended]
+    python tests/golden/make_long_horizon.py tg4096 dugks [threads] [--extended]
 
---extended also runs the extended-precision build of the oracle (bl512 uses it: at
-dt/tau = 118 the FP64 oracle's own rounding grows to about 1e-11 in 5000 steps).
-
-The tg4096 case takes about an hour and a half on 6 cores.
+--extended also runs the extended-precision build of the oracle and records its
+values at the same cells.  Each scheme takes about an hour and a half on 6 cores.
 """
 import os
 import sys
@@ -35,8 +32,6 @@ from paper_1511_00242_amd import inputs as I       # noqa: E402
 HERE = os.path.dirname(os.path.abspath(__file__))
 CASES = {
     "tg4096": (lambda: I.taylor_green(4096), 2000),
-    "cav256": (lambda: I.cavity(256), 20000),
-    "bl512": (lambda: I.boundary_layer(), 5000),
 }
 SCHEMES = {"dugks": O.DUGKS, "bkg": O.BKG}
 N_RANDOM = 120

@@ -1,8 +1,9 @@
 """GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle.
 
-Bars: FP64 relative L2 <= 1e-12 on f~ (all 9 directions) and on u; FP32
-deviation storage <= 1e-5 on u.  Relative L2: ||X_gpu - X_oracle|| / ||X_oracle||
-over all cells.
+Bars: FP64 <= 1e-12 on f~ (all 9 directions) and on u; FP32 deviation storage
+<= 1e-5 on u.  Each is held both as a relative L2 norm ||X_gpu - X_oracle|| /
+||X_oracle|| over all cells and as a largest-element ratio max|X_gpu - X_oracle| /
+max|X_oracle| (``rel`` returns the larger of the two).
 """
 import math
 import os
@@ -33,20 +34,35 @@ def _device():
 
 
 def rel(a, b):
-    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+    """The error measure of every comparison here: the larger of the relative L2 norm
+    ||a - b|| / ||b|| over all cells and the largest-element ratio max|a - b| / max|b|,
+    so that no bar rests on a norm alone (an error in one cell of a large mesh barely
+    moves the L2 norm)."""
+    d = (a - b).ravel()
+    return float(max(np.linalg.norm(d) / np.linalg.norm(b.ravel()), np.max(np.abs(d)) / np.max(np.abs(b))))
 
 
-def assert_fp64(g, ref, ext, label):
-    """FP64 bar: rel L2 <= 1e-12 against the FP64 oracle; where the FP64 oracle's own
-    rounding has grown past 1e-13 (its distance from the extended-precision build of the
-    same oracle), the GPU must be as close to the extended result as the FP64 oracle is,
-    within a factor 2, or within 1e-12 of it."""
+def assert_fp64(g, ref, ext, label, amplifying=False):
+    """FP64 bar on a long or ill-conditioned run: relative L2 and largest-element ratio
+    <= 1e-12 against the FP64 oracle while its own rounding stays below 1e-13 (its
+    distance from the extended-precision build of the same oracle source); past that,
+    the same 1e-12 against the extended-precision result.
+
+    amplifying: the one named exception, the central interface value of Sec. 2.4
+    (Eq. cfd1).  Without the half-step trace its transport is forward Euler in time,
+    which multiplies any perturbation of the state each step (a one-ulp difference
+    grows to about 2.5e-12 over 1000 steps of Taylor-Green 32^2), so no FP64 code
+    that rounds in another order can stay within 1e-12 of the exact result; there the
+    GPU must be at least as close to the extended-precision result as the FP64 oracle
+    is, within a factor of 2."""
     e, e_ora, e_gpu = rel(g, ref), rel(ref, ext), rel(g, ext)
     print(f"{label}: GPU vs FP64 oracle {e:.2e}; vs extended: FP64 oracle {e_ora:.2e}, GPU {e_gpu:.2e}")
     if e_ora <= 1e-13:
-        assert e < TOL64
+        assert e <= TOL64, label
+    elif amplifying:
+        assert e_gpu <= max(TOL64, 2.0 * e_ora), label
     else:
-        assert e_gpu <= max(TOL64, 2.0 * e_ora)
+        assert e_gpu <= TOL64, label
 
 
 def u_rel(ora, fa, fb):
@@ -487,7 +503,7 @@ def test_collision_free_interface_values(scheme, oscheme):
     # the central form amplifies rounding (forward-Euler transport): an FP64 perturbation
     # of one ulp grows to ~2.5e-12 in 1000 steps, so the bar uses the extended oracle
     ext = O.Case(tg.xf, tg.yf, tg.rt, tg.tau, tg.dt, tg.bcs, threads=1, extended=True).run(f0, oscheme, 1000)
-    assert_fp64(g, ref, ext, f"sec2.4 scheme={scheme} tg32")
+    assert_fp64(g, ref, ext, f"sec2.4 scheme={scheme} tg32", amplifying=scheme == L.LBFV_CENTRAL)
     # FP32: the central form multiplies rounding by ~2e4 over 1000 steps (see above), so
     # its FP32 run is compared after 200 steps, where that factor is below 10
     n32 = 200 if scheme == L.LBFV_CENTRAL else 1000
@@ -630,43 +646,48 @@ def test_two_steps_per_launch_with_sides_equal_two_launches(nx, ny):
                         assert rel(outs[1], ora.run(f0, oscheme, n)) < TOL64, (nx, ny, k, scheme)
 
 
-def test_bkg_parameter_copy_follows_side_changes():
-    """The BKG kernels with sides read their parameters from a device copy that is refreshed
-    only when they change: changing a wall velocity, a side kind and the scheme between
-    launches and graph replays gives the same bits with one and two steps per launch, and
-    the oracle's result."""
+ALL_SCHEMES = SCHEMES + [(L.LBFV_CENTRAL, O.CENTRAL), (L.LBFV_UPWIND, O.UPWIND)]
+
+
+@pytest.mark.parametrize("compute,storage", [(L.LBFV_FP64, L.LBFV_STORE_NATIVE),
+                                             (L.LBFV_FP32, L.LBFV_STORE_DEV_FP32)])
+@pytest.mark.parametrize("scheme,oscheme", ALL_SCHEMES)
+def test_parameter_copy_follows_side_changes(scheme, oscheme, compute, storage):
+    """The kernels with sides that read their parameters from a device copy (refreshed
+    only when the parameters change) follow changes of a wall velocity, a side kind and
+    the scheme between launches and graph replays: graph replays run before and after
+    every set_sides call (segments of 70 and 66 steps against graphs of 32 launches),
+    one and two steps per launch give the same bits, and the oracle run segment by
+    segment with each segment's sides gives the same result (FP64 on f~, FP32 on u)."""
     w = I.cavity(40, re=100.0, stretched=True)
     ora = oracle_case(w, 1)
     f0 = perturbed_state(ora, w, 23)
     lid2 = [("wall", 0.0, 0.0), ("wall", 0.0, 0.0), ("wall", 0.0, 0.0), ("wall", 0.05, 0.0)]
     open_e = [("wall", 0.0, 0.0), ("outflow", 1), ("wall", 0.0, 0.0), ("wall", 0.1, 0.0)]
+    other, oother = (L.LBFV_BKG, O.BKG) if scheme == L.LBFV_DUGKS else (L.LBFV_DUGKS, O.DUGKS)
+    segments = [(w.bcs, scheme, oscheme, 70), (lid2, scheme, oscheme, 70), (lid2, other, oother, 4),
+                (open_e, scheme, oscheme, 66), (w.bcs, scheme, oscheme, 5)]
     outs = []
     for tb in (1, 2):
-        with L.Context(w.xf, w.yf, w.tau, w.dt, bcs=w.bcs) as ctx:
+        with L.Context(w.xf, w.yf, w.tau, w.dt, bcs=w.bcs, compute=compute, storage=storage) as ctx:
             ctx.set_f(f0)
             ctx.set_time_block(tb)
-            ctx.bkg_step(70)          # graph replays of the default graph length, then launches
-            ctx.set_sides(lid2)
-            ctx.bkg_step(9)
-            ctx.dugks_step(4)
-            ctx.set_sides(open_e)
-            ctx.bkg_step(66)
-            ctx.set_sides(w.bcs)
-            ctx.bkg_step(5)
+            for bcs, sc, _, n in segments:
+                ctx.set_sides(bcs)
+                ctx.step(sc, n)
             outs.append(ctx.get_f())
     assert np.all(np.isfinite(outs[0]))
     assert np.array_equal(outs[0], outs[1]), rel(outs[1], outs[0])
-    # both time blocks read the copy (one-step kernels with sides do too): the oracle, run
-    # segment by segment with each segment's sides, pins the sequence itself
-    def seg(bcs, f, scheme, n):
+    f = f0
+    for bcs, _, osc, n in segments:
         wb = I.Workload("seg", w.xf, w.yf, w.tau, w.dt, bcs, w.rho, w.ux, w.uy)
-        return oracle_case(wb, 1).run(f, scheme, n)
-    f = seg(w.bcs, f0, O.BKG, 70)
-    f = seg(lid2, f, O.BKG, 9)
-    f = seg(lid2, f, O.DUGKS, 4)
-    f = seg(open_e, f, O.BKG, 66)
-    f = seg(w.bcs, f, O.BKG, 5)
-    assert rel(outs[1], f) < TOL64, rel(outs[1], f)
+        f = oracle_case(wb, 1).run(f, osc, n)
+    ef, eu = rel(outs[1], f), u_rel(ora, outs[1], f)
+    print(f"parameter copy scheme={scheme} compute={compute}: f {ef:.2e} u {eu:.2e}")
+    if compute == L.LBFV_FP64:
+        assert ef <= TOL64 and eu <= TOL64
+    else:
+        assert eu <= TOL32_U
 
 
 def test_time_block_switch_keeps_state_and_falls_back_off_periodic():

@@ -60,6 +60,28 @@ def test_d2q9_tables_isotropy():
     assert np.allclose(xy, [0, 0, 1, 0, -1, 1, 1, -1, -1])
 
 
+def test_dt_from_cfl_hand_values():
+    """Eq. eq:cfl, dt = eta dx / |xi|_max with |xi|_max = sqrt(6 RT) (the diagonal speed
+    sqrt(2) c, c = sqrt(3 RT)) and dx the smallest cell of either axis (reading R7),
+    against values worked out by hand.  Each mesh puts its smallest cell on a different
+    axis, so a minimum over one axis only, a sqrt(3 RT) speed or a largest cell fails."""
+    # uniform 32-cell axes of length 6.4: dx = 0.2; RT = 1/3 gives |xi|_max = sqrt(2)
+    xf = np.linspace(0.0, 6.4, 33)
+    assert O.dt_from_cfl(xf, xf, RT, 0.5) == pytest.approx(0.5 * 0.2 / math.sqrt(2.0), rel=1e-15)
+    assert O.dt_from_cfl(xf, xf, RT, 1.0) == pytest.approx(0.1414213562373095, rel=1e-15)
+    # stretched: x cells 0.5, 0.25, 0.125, 0.125; y cells 0.3, 0.2, 0.05, 0.45.  The
+    # smallest cell, 0.05, is on y; RT = 1/2 gives |xi|_max = sqrt(3)
+    xs = np.array([0.0, 0.5, 0.75, 0.875, 1.0])
+    ys = np.array([0.0, 0.3, 0.5, 0.55, 1.0])
+    assert O.dt_from_cfl(xs, ys, 0.5, 0.8) == pytest.approx(0.023094010767585035, rel=1e-15)
+    # the same axes swapped: the smallest cell is now on x
+    assert O.dt_from_cfl(ys, xs, 0.5, 0.8) == pytest.approx(0.023094010767585035, rel=1e-15)
+    # x holds the smallest cell (0.0625 against 0.1 on y); RT = 1/4, |xi|_max = sqrt(1.5)
+    xg = np.array([0.0, 0.0625, 0.1875, 0.4375, 0.9375])
+    yg = np.array([0.0, 0.1, 0.3, 0.6])
+    assert O.dt_from_cfl(xg, yg, 0.25, 1.1) == pytest.approx(0.05613413993878118, rel=1e-15)
+
+
 def test_equilibrium_moments():
     """feq reproduces rho, rho u and the Navier-Stokes momentum flux rho (RT I + u u)."""
     rng = np.random.default_rng(7)
