@@ -165,6 +165,22 @@ int lbfv_moments(lbfv_ctx *ctx, double *rho, double *ux, double *uy);
 int lbfv_totals(lbfv_ctx *ctx, double out[3]);
 int lbfv_residual(lbfv_ctx *ctx, double *r);
 
+/* lbfv_totals without any allocation, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Enqueues the totals reduction on the context's stream and returns without waiting.
+ * dev_out: caller-owned device memory of 4 doubles; it receives sum rho |V|,
+ * sum rho u |V|, sum rho v |V| (the same kernels and summation order as lbfv_totals,
+ * hence the same bits) and the number of cells holding a non-finite value (the
+ * context's unstable flag is not updated: the caller reads dev_out[3]).  The per-block
+ * partial sums go to a fixed scratch array of the library, 1024 x 6 doubles (48 KiB),
+ * one per GPU, held until the process ends; that need does not depend on the mesh size.
+ * Calls that overlap on one GPU (any contexts, any streams) race on the array, so they
+ * must be ordered (one stream, or events).  ESTATE before the context's mesh metrics
+ * are on the device (the first step or lbfv_totals call uploads them, and that upload
+ * allocates) or before a state exists; EINVAL for a NULL pointer or when the current
+ * device is not the one the context was created on. */
+int lbfv_totals_device(lbfv_ctx *ctx, double *dev_out);
+
 /* Execution shape of the step kernel: rows of the row block one wavefront marches
  * through, and wavefronts per workgroup (1, 2 or 4).  0 keeps the current value. */
 int lbfv_set_tile(lbfv_ctx *ctx, int32_t rows, int32_t waves_per_block);

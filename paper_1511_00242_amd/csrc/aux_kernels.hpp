@@ -145,6 +145,7 @@ __global__ void moments_kernel(StepParams<T> P, int parity, double *rho, double 
 // mode bit 1: residual terms (and u_prev := u).
 constexpr int RED_BLOCK = 256;
 constexpr int RED_N = 6;
+constexpr int RED_GRID = 1024;   // blocks of the check reduction (a fixed grid: a fixed summation order)
 
 // Wavefront butterfly: after it every lane holds the sum of the 64 lanes (each step adds
 // a + b in one lane and b + a in its partner, so the lanes agree bit for bit).
@@ -205,13 +206,28 @@ __global__ __launch_bounds__(RED_BLOCK) void reduce_kernel(StepParams<T> P, int 
     block_sum(v, sh, partial + (int64_t)blockIdx.x * RED_N);
 }
 
-__global__ __launch_bounds__(RED_BLOCK) void reduce_final_kernel(const double *partial, int nblocks, double *out) {
+// compact = 0: out[0..5] as above; compact = 1: out[0..3] = totals[0..2] and the
+// non-finite count (the residual sums are not formed in that mode).
+__global__ __launch_bounds__(RED_BLOCK) void reduce_final_kernel(const double *partial, int nblocks, double *out,
+                                                                 int compact) {
     __shared__ double sh[RED_N][RED_WAVES];
+    __shared__ double res[RED_N];
     double v[RED_N] = {0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nblocks; b += RED_BLOCK)
 #pragma unroll
         for (int q = 0; q < RED_N; ++q) v[q] += partial[(int64_t)b * RED_N + q];
-    block_sum(v, sh, out);
+    block_sum(v, sh, res);
+    if (threadIdx.x == 0) {
+        if (compact) {
+            out[0] = res[0];
+            out[1] = res[1];
+            out[2] = res[2];
+            out[3] = res[5];
+        } else {
+#pragma unroll
+            for (int q = 0; q < RED_N; ++q) out[q] = res[q];
+        }
+    }
 }
 
 // Re-encode a state for a new reference state: x_a += F_a(old) - F_a(new), in FP64 and

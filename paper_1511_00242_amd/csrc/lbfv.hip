@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -74,6 +75,7 @@ struct lbfv_ctx {
     HostCase hc;
     int check_every = 1000;
     hipStream_t stream = nullptr;
+    int device = -1;                 // the device current at lbfv_create
     bool has_state = false;
     bool unstable = false;
     int64_t steps = 0, steps_at_check = 0;
@@ -690,7 +692,7 @@ int build_graph(lbfv_ctx *c, int scheme, int parity0, const double ext[4], bool 
 
 int ensure_reduction(lbfv_ctx *c) {
     if (c->d_partial) return LBFV_OK;
-    c->red_blocks = 1024;
+    c->red_blocks = RED_GRID;
     HIPCHK(hipMalloc((void **)&c->d_partial, sizeof(double) * RED_N * c->red_blocks));
     HIPCHK(hipMalloc((void **)&c->d_out, sizeof(double) * RED_N));
     HIPCHK(hipHostMalloc((void **)&c->h_out, sizeof(double) * RED_N, hipHostMallocDefault));
@@ -706,7 +708,7 @@ void launch_reduce_t(lbfv_ctx *c, const double ext[4], int mode) {
     hipLaunchKernelGGL((reduce_kernel<T, S>), dim3(c->red_blocks), dim3(RED_BLOCK), 0, c->stream, P, h.cur, h.d_dx,
                        h.d_dy, c->d_uprev, mode, h.ref(), h.c, c->d_partial);
     hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(RED_BLOCK), 0, c->stream, c->d_partial, c->red_blocks,
-                       c->d_out);
+                       c->d_out, 0);
 }
 
 int launch_reduce(lbfv_ctx *c, int mode) {
@@ -898,6 +900,50 @@ int staging(lbfv_ctx *c, size_t count, double **p) {
 
 }  // namespace
 
+// ------------------------------------------------------------------ allocation-free totals
+// Scratch of lbfv_totals_device: the per-block partial sums of the check reduction (the
+// grid and kernels of lbfv_totals, so both give the same bits).  Its need is fixed
+// (RED_GRID blocks x RED_N sums) whatever the mesh size.  Each GPU holds its own copy
+// until the process ends; calls that overlap on one GPU race on it.  Host code never
+// passes this name to a kernel: it takes the device address found by
+// hipGetSymbolAddress, per device.
+constexpr int SCRATCH_DOUBLES = RED_GRID * RED_N;   // 48 KiB
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// the address of `scratch` on the current device, looked up once per device
+int scratch_address(lbfv_ctx *c, int dev, double **p) {
+    if (dev < 0 || dev >= kMaxDevices) return c->fail(LBFV_EUNSUPPORTED, "lbfv_totals_device: device index too large");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return c->fail(LBFV_EHIP, std::string("lbfv_totals_device: hipGetSymbolAddress(scratch): ") +
+                                          hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = (double *)ptr;
+    }
+    *p = g_scratch_ptr[dev];
+    return LBFV_OK;
+}
+
+template <typename T, typename S>
+void launch_reduce_into(lbfv_ctx *c, const double ext[4], double *partial, double *out) {
+    HostCase &h = c->hc;
+    double e[4] = {ext[0], ext[1], ext[2], ext[3]};
+    StepParams<T> P = make_params<T>(h, e);
+    hipLaunchKernelGGL((reduce_kernel<T, S>), dim3(RED_GRID), dim3(RED_BLOCK), 0, c->stream, P, h.cur, h.d_dx,
+                       h.d_dy, (double *)nullptr, 0, h.ref(), h.c, partial);
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(RED_BLOCK), 0, c->stream, partial, RED_GRID, out, 1);
+}
+}  // namespace
+
 extern "C" {
 
 int lbfv_create(const lbfv_mesh *mesh, const lbfv_velset *vel, double tau, double dt, const lbfv_opts *opts,
@@ -928,6 +974,10 @@ int lbfv_create(const lbfv_mesh *mesh, const lbfv_velset *vel, double tau, doubl
     init_host_case(c->hc, mesh, vel, tau, dt, o.compute, o.storage, o.rho0);
     c->check_every = o.check_every;
     c->stream = (hipStream_t)o.hip_stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        (void)hipGetLastError();
+        c->device = -1;
+    }
     *ctx = c;
     return LBFV_OK;
 }
@@ -1180,6 +1230,32 @@ int lbfv_totals(lbfv_ctx *c, double out[3]) {
     out[2] = c->h_out[2];
     if (c->h_out[5] > 0) c->unstable = true;
     if (c->unstable) return c->fail(LBFV_EUNSTABLE, "a non-finite value was found");
+    return LBFV_OK;
+}
+
+int lbfv_totals_device(lbfv_ctx *c, double *dev_out) {
+    if (!c) return LBFV_EINVAL;
+    if (!dev_out) return c->fail(LBFV_EINVAL, "lbfv_totals_device: NULL output");
+    if (!c->has_state) return c->fail(LBFV_ESTATE, "no state");
+    if (c->hc.metrics_dirty)
+        return c->fail(LBFV_ESTATE, "lbfv_totals_device: the mesh metrics are not on the device yet (step the "
+                                    "context or call lbfv_totals once; their upload allocates)");
+    static_assert(RED_GRID * RED_N <= SCRATCH_DOUBLES, "scratch too small for the reduction grid");
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != c->device) return c->fail(LBFV_EINVAL, "lbfv_totals_device: the context's device must be current");
+    double *partial = nullptr;
+    int st = scratch_address(c, dev, &partial);
+    if (st) return st;
+    double ext[4];
+    current_ext(c->hc, ext);
+    switch (c->hc.variant) {
+    case V_F64: launch_reduce_into<double, double>(c, ext, partial, dev_out); break;
+    case V_F32: launch_reduce_into<float, float>(c, ext, partial, dev_out); break;
+    case V_BF16: launch_reduce_into<float, __bf16>(c, ext, partial, dev_out); break;
+    default: launch_reduce_into<float, _Float16>(c, ext, partial, dev_out); break;
+    }
+    HIPCHK(hipGetLastError());
     return LBFV_OK;
 }
 

@@ -33,7 +33,7 @@ EXPORTS = (
     "lbfv_init_equilibrium",
     "lbfv_init_chapman_enskog", "lbfv_set_f",
     "lbfv_get_f", "lbfv_bind_buffers", "lbfv_required_bytes", "dugks_step", "bkg_step", "lbfv_step",
-    "lbfv_moments", "lbfv_totals", "lbfv_residual", "lbfv_set_tile", "lbfv_get_tile",
+    "lbfv_moments", "lbfv_totals", "lbfv_totals_device", "lbfv_residual", "lbfv_set_tile", "lbfv_get_tile",
     "lbfv_set_time_block", "lbfv_get_time_block", "lbfv_set_reference_velocity",
     "lbfv_get_reference_velocity",
     "lbfv_autotune", "lbfv_strerror", "lbfv_last_error", "lbfv_batch_create",
@@ -108,6 +108,7 @@ def lib():
             "lbfv_step": ([vp, ip, C.c_int32], ip),
             "lbfv_moments": ([vp, dp, dp, dp], ip),
             "lbfv_totals": ([vp, dp], ip),
+            "lbfv_totals_device": ([vp, vp], ip),
             "lbfv_residual": ([vp, dp], ip),
             "lbfv_set_tile": ([vp, C.c_int32, C.c_int32], ip),
             "lbfv_set_time_block": ([vp, C.c_int32], ip),
@@ -312,6 +313,11 @@ class Context:
         out = np.zeros(3)
         _check(lib().lbfv_totals(self.h, _p(out)), self.h)
         return out
+
+    def totals_device(self, dev_out: int):
+        """lbfv_totals_device: enqueue the totals into 4 doubles of device memory at
+        `dev_out` (a device address, e.g. a torch tensor's data_ptr()); no allocation."""
+        _check(lib().lbfv_totals_device(self.h, C.c_void_p(int(dev_out))), self.h)
 
     def residual(self) -> float:
         r = C.c_double()

@@ -97,6 +97,9 @@ def test_state_errors_before_any_device_work():
     assert L.lib().lbfv_set_time_block(ctx.h, 3) == L.LBFV_EINVAL
     L._check(L.lib().lbfv_set_time_block(ctx.h, 2), ctx.h)      # periodic, no state yet
     L._check(L.lib().lbfv_set_time_block(ctx.h, 1), ctx.h)
+    # the allocation-free totals need a state (and the mesh metrics on the device)
+    assert L.lib().lbfv_totals_device(ctx.h, None) == L.LBFV_EINVAL
+    assert L.lib().lbfv_totals_device(None, None) == L.LBFV_EINVAL
     assert L.lib().dugks_step(ctx.h, -1) == L.LBFV_EINVAL
     assert L.lib().lbfv_step(ctx.h, 4, 1) == L.LBFV_EINVAL
     assert L.lib().lbfv_step(ctx.h, -1, 1) == L.LBFV_EINVAL
