@@ -29,6 +29,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 HEADLINE_TILE = (142, 2)        # rows per block, waves per block of the timed 4096^2 step, and
 HEADLINE_TIME_BLOCK = 2        # steps per launch (fixed so that the committed counter profile
                                # describes the same launches)
+HEADLINE_PAIRS = 0             # two steps per launch: one wave (0) or a pair of waves (1) per item
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_dugks_fp64_taylor_green_4096.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1511_00242_amd", "csrc", "kernels.hpp")
 BYTES = {"f64": 144, "f32": 72, "bf16": 36, "f16": 36}   # algorithmic bytes per cell-step (9 reads + 9 writes)
@@ -55,6 +56,8 @@ def parse():
                    help="time_block,rows,wave_per_item (0/1) of the batch (skips its autotuner)")
     p.add_argument("--time-block", type=int, default=HEADLINE_TIME_BLOCK,
                    help="steps per launch with --tile on doubly periodic meshes (1 or 2)")
+    p.add_argument("--pairs", type=int, default=HEADLINE_PAIRS,
+                   help="with --tile and two steps per launch: a pair of waves per work item (1) or one (0)")
     p.add_argument("--copy-probe-mb", type=int, default=0,
                    help="also run a plain device copy of this many MiB (calibrates HBM byte counters)")
     p.add_argument("--cavity-residual", action="store_true",
@@ -127,7 +130,7 @@ def timed_steps(ctx, scheme, steps, warmup, stream):
 
 
 def run_single(name, w, scheme, compute, storage, steps, warmup, check_every, stream, tile=None,
-               time_block=1, burn_s=0.0):
+               time_block=1, burn_s=0.0, pairs=0):
     """Time `steps` steps of one workload; a fixed launch shape, or the autotuner's choice
     of shape and time block (one or two steps per launch).
     burn_s: wall time of GPU burn-in before the warm-up (the state is re-initialised after
@@ -141,6 +144,7 @@ def run_single(name, w, scheme, compute, storage, steps, warmup, check_every, st
     if tile:
         ctx.set_time_block(time_block)
         ctx.set_tile(*tile)
+        ctx.set_wave_pairs(pairs)
     else:
         trial = trial_steps_for(ctx, scheme, stream)
         ctx.autotune(scheme, trial, os.environ.get("LBFV_TUNE_CACHE"))
@@ -153,12 +157,13 @@ def run_single(name, w, scheme, compute, storage, steps, warmup, check_every, st
     ms, wall_ms = timed_steps(ctx, scheme, steps, warmup, stream)
     rows, wpb = ctx.get_tile()
     tb = ctx.get_time_block()
+    pr = ctx.get_wave_pairs()
     tot = ctx.totals()                       # also re-checks for non-finite values
     ctx.close()
     cells = w.nx * w.ny
     per = ms / steps
     out = dict(name=name, ms_per_step=per, mlups=cells / (per * 1e-3) / 1e6, wall_ms=wall_ms,
-               tile=[rows, wpb], time_block=tb, mass=tot[0])
+               tile=[rows, wpb], time_block=tb, wave_pairs=int(pr), mass=tot[0])
     if tune:
         out["autotune"] = tune
     if burn:
@@ -394,7 +399,7 @@ def kernel_code_hash(path=KERNEL_SOURCE):
     return hashlib.sha256(" ".join(text.split()).encode()).hexdigest()
 
 
-def profiled_traffic(tile, time_block, ms_per_step):
+def profiled_traffic(tile, time_block, ms_per_step, pairs=0):
     """HBM traffic of the headline kernel from the committed rocprofv3 counter summary:
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the same counters read for a
     plain 1 GiB device copy.  None when the kernel source or the launch shape changed since."""
@@ -407,7 +412,7 @@ def profiled_traffic(tile, time_block, ms_per_step):
             kv[k.strip()] = v.strip()
     try:
         if (kv.get("kernel_code_sha256") != kernel_code_hash() or kv.get("tile") != f"{tile[0]},{tile[1]}"
-                or kv.get("time_block", "1") != str(time_block)):
+                or kv.get("time_block", "1") != str(time_block) or kv.get("wave_pairs", "0") != str(pairs)):
             return None, None
         b = (float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
              + float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"])) * 1024.0
@@ -559,16 +564,17 @@ def main():
     w = I.taylor_green(a.n)
     head = run_single("dugks_fp64", w, L.LBFV_DUGKS, L.LBFV_FP64, L.LBFV_STORE_NATIVE, steps, a.warmup,
                       a.check_every, stream, tile or HEADLINE_TILE, a.time_block if tile else HEADLINE_TIME_BLOCK,
-                      burn_s=a.burn_in)
+                      burn_s=a.burn_in, pairs=a.pairs if tile else HEADLINE_PAIRS)
     print(f"[bench] dugks fp64 {a.n}^2: {head['ms_per_step']:.4f} ms/step {head['mlups']:.0f} MLUPS",
           file=sys.stderr, flush=True)
     # the roofline figure divides by the step kernel's own average duration: the same launches
     # without the periodic check reductions
     kern = run_single("dugks_fp64_kernel", w, L.LBFV_DUGKS, L.LBFV_FP64, L.LBFV_STORE_NATIVE, steps,
-                      a.warmup, 0, stream, tuple(head["tile"]), head["time_block"])
+                      a.warmup, 0, stream, tuple(head["tile"]), head["time_block"], pairs=head["wave_pairs"])
     cells = w.nx * w.ny
     gbs = cells * BYTES["f64"] / (kern["ms_per_step"] * 1e-3) / 1e9
-    traffic_gbs, traffic_bytes = profiled_traffic(head["tile"], head["time_block"], kern["ms_per_step"])
+    traffic_gbs, traffic_bytes = profiled_traffic(head["tile"], head["time_block"], kern["ms_per_step"],
+                                                  head["wave_pairs"])
 
     variants = {}
     if not a.no_variants:
@@ -644,12 +650,13 @@ def main():
         "config": {"workload": f"taylor_green_{a.n}x{a.n}_dugks_fp64", "nx": a.n, "ny": a.n,
                    "scheme": "dugks", "precision": "fp64", "boundary": "periodic",
                    "check_every": a.check_every, "tile_rows_waves": head["tile"],
-                   "steps_per_launch": head["time_block"],
+                   "steps_per_launch": head["time_block"], "wave_pairs": head["wave_pairs"],
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": traffic_gbs,
                      "traffic_bytes_per_launch": traffic_bytes,
-                     "kernel": ("lbfv::step2_kernel<double,double,DUGKS>" if head["time_block"] == 2
+                     "kernel": (("lbfv::step2p_kernel<double,double,DUGKS>" if head["wave_pairs"]
+                                 else "lbfv::step2_kernel<double,double,DUGKS>") if head["time_block"] == 2
                                 else "lbfv::step_kernel<double,double,DUGKS>"),
                      "steps_per_launch": head["time_block"],
                      "kernel_ms": kern["ms_per_step"],

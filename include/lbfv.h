@@ -185,6 +185,16 @@ int lbfv_totals_device(lbfv_ctx *ctx, double *dev_out);
  * through, and wavefronts per workgroup (1, 2 or 4).  0 keeps the current value. */
 int lbfv_set_tile(lbfv_ctx *ctx, int32_t rows, int32_t waves_per_block);
 int lbfv_get_tile(const lbfv_ctx *ctx, int32_t *rows, int32_t *waves_per_block);
+/* Work split of two steps per launch: 0 (default) one wavefront per work item (strip x
+ * row block) advances both steps; 1 a workgroup of two wavefronts per item, the first
+ * advancing the first step (with its ghost cells) and handing each new row to the second
+ * through LDS, which advances the second step and stores it.  Each then holds one step's
+ * rows in registers (about half), so more wavefronts fit per SIMD and each wave's chain
+ * of dependent work is half as long.  The same bits either way; waves_per_block of
+ * lbfv_set_tile does not apply to the pair form.  Ignored with one step per launch.
+ * EINVAL unless 0 or 1. */
+int lbfv_set_wave_pairs(lbfv_ctx *ctx, int32_t on);
+int lbfv_get_wave_pairs(const lbfv_ctx *ctx, int32_t *on);
 /* Time steps per launch of the single-case step: 1 or 2.  With 2, each wavefront reads its
  * strip of the state once, keeps the intermediate step in registers (ghost cells, wall and
  * symmetry faces of both steps included) and writes the second, so a step moves half the

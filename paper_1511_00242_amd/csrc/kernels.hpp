@@ -268,25 +268,30 @@ __device__ __forceinline__ Mom<T> moments(const T (&x)[9], T rho0, T m0x, T m0y)
 }
 // The equilibrium deviation from the moments: rho P_a's second-order part is
 // rho (4.5 (e.u-hat)^2 - 1.5 |u-hat|^2) = (4.5 (e.M)^2 - 1.5 |M|^2) / rho, so neither u-hat
-// nor e.u-hat is formed.
+// nor e.u-hat is formed.  The unweighted deviations of direction A and of its reverse
+// REV[A] are formed at once: their second-order parts are equal ((e.M)^2 does not see
+// the sign of e), so both are s +- 3 e.m with s = drho + q / rho formed once (4
+// instructions saved per pair, a tenth of the step's arithmetic with the two face mixes
+// counted).  A = 0 (no reverse): s.
 template <typename T>
-__device__ __forceinline__ T dfeq_unweighted(int A, const Mom<T> &m, T q0) {
+__device__ __forceinline__ void dfeq_pair_unweighted(int A, const Mom<T> &m, T q0, T &Qa, T &Qr) {
     const T eM = edot<T>(A, m.Mx, m.My);
     const T em = kRefVel<T> ? edot<T>(A, m.mx, m.my) : eM;
-    const T q = fma((T)4.5 * eM, eM, -m.msq15);
-    return fma(m.inv, q, fma((T)3, em, m.drho) - (kRefVel<T> ? q0 : (T)0));
+    const T q = A == 0 ? -m.msq15 : fma((T)4.5 * eM, eM, -m.msq15);
+    const T s = fma(m.inv, q, kRefVel<T> ? m.drho - q0 : m.drho);
+    Qa = A == 0 ? s : fma((T)3, em, s);
+    Qr = A == 0 ? s : fma((T)-3, em, s);
 }
+// dfeq - x from the unweighted deviation Q.  FP64 folds the weight into one fused
+// multiply-add (one rounding, one instruction fewer per direction); FP32 keeps the
+// two-term weight product.
 template <typename T>
-__device__ __forceinline__ T dfeq(int A, const Mom<T> &m, T q0) {
-    return wmul<T>(A, dfeq_unweighted(A, m, q0));
+__device__ __forceinline__ T wsub(int A, T Q, T x) {
+    if (sizeof(T) == 8) return fma((T)wgt(A), Q, -x);
+    return wmul<T>(A, Q) - x;
 }
-// dfeq - x.  FP64 folds the weight into one fused multiply-add (one rounding, one
-// instruction fewer per direction); FP32 keeps the two-term weight product.
-template <typename T>
-__device__ __forceinline__ T dfeq_sub(int A, const Mom<T> &m, T q0, T x) {
-    if (sizeof(T) == 8) return fma((T)wgt(A), dfeq_unweighted(A, m, q0), -x);
-    return dfeq(A, m, q0) - x;
-}
+// The representative of each direction pair (A, REV[A]): 0 (alone), 1, 2, 5, 6.
+__device__ __forceinline__ constexpr int pair_rep(int k) { return k == 0 ? 0 : (k == 1 ? 1 : (k == 2 ? 2 : (k == 3 ? 5 : 6))); }
 
 // ---------------------------------------------------------------- the strip march
 // BND = false compiles out every ghost-cell and bounce-back path; it is used when both
@@ -387,9 +392,15 @@ struct March {
     }
     __device__ __forceinline__ void cell_t(const T (&x)[9], T (&phi)[9], T (&psi)[9]) const {
         const Mom<T> m = moments(x, P.rho0, P.m0x, P.m0y);
+        T Q[9];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const int A = pair_rep(k);
+            dfeq_pair_unweighted(A, m, P.q0[A], Q[A], Q[REV[A]]);
+        }
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
-            const T d = dfeq_sub(a, m, P.q0[a], x[a]);
+            const T d = wsub(a, Q[a], x[a]);
             if (SCHEME == SCHEME_DUGKS) {
                 phi[a] = fma(P.cb, d, x[a]);
                 psi[a] = fma(P.cd, d, x[a]);
@@ -479,11 +490,15 @@ struct March {
     __device__ __forceinline__ void face_mix(T (&fb)[9]) const {
         if (SCHEME == SCHEME_DUGKS) {
             const Mom<T> m = moments<T, false>(fb, P.rho0, P.m0x, P.m0y);
+            // the directions crossing the face come in reverse pairs: (1, 3) or (2, 4), (5, 7), (6, 8)
 #pragma unroll
-            for (int a = 0; a < 9; ++a) {
-                if ((AX == 0 ? EX[a] : EY[a]) != 0) {
-                    fb[a] = fma(P.m2, dfeq_sub(a, m, P.q0[a], fb[a]), fb[a]);
-                }
+            for (int k = 0; k < 3; ++k) {
+                const int A = k == 0 ? (AX == 0 ? 1 : 2) : (k == 1 ? 5 : 6);
+                const int R = REV[A];
+                T Qa, Qr;
+                dfeq_pair_unweighted(A, m, P.q0[A], Qa, Qr);
+                fb[A] = fma(P.m2, wsub(A, Qa, fb[A]), fb[A]);
+                fb[R] = fma(P.m2, wsub(R, Qr, fb[R]), fb[R]);
             }
         }
     }
@@ -743,6 +758,96 @@ struct March {
         }
     }
 
+    // ---- two steps per pass split over a pair of waves (HALO = 2, periodic mesh).  The
+    // producer wave advances level 0 at rows j0-1 .. j1 exactly as run2 does and hands each
+    // level-1 row to the consumer wave through a two-slot ring in LDS; the consumer forms
+    // level-1 phi / psi from it and advances level 1 at rows j0 .. j1-1, which it stores.
+    // Each wave then holds one level's rows, half of run2's registers.  One workgroup
+    // barrier per row orders the ring: in round t the producer writes slot t & 1 while the
+    // consumer reads slot (t-1) & 1, the row of round t-1, and the slot the producer writes
+    // next was read before the barrier between them.  Both waves pass j1 - j0 + 3 barriers
+    // (the producer one after its last row, the consumer one before its first).  Same
+    // arithmetic on the same values as run2, so the same bits.
+    __device__ __forceinline__ void ring_put(T *ring, int slot, const T (&v)[9]) const {
+        T *p = ring + slot * (9 * 64) + lane;
+#pragma unroll
+        for (int a = 0; a < 9; ++a) p[a * 64] = v[a];
+    }
+    __device__ __forceinline__ void ring_get(const T *ring, int slot, T (&v)[9]) const {
+        const T *p = ring + slot * (9 * 64) + lane;
+#pragma unroll
+        for (int a = 0; a < 9; ++a) v[a] = p[a * 64];
+    }
+    // producer, level 0 at row k: Pm, P0, Pp = phi rows k-1, k, k+1; S0 = psi row k; Sm
+    // receives psi of row k+2 (with phi in Pm) when a next row is needed
+    __device__ __forceinline__ void produce_row(int k, int j0, int j1, T (&Pm)[9], T (&P0)[9], T (&Pp)[9],
+                                                T (&Sm)[9], T (&S0)[9], T (&fS)[9], S (&R)[9], T *ring, int t) {
+        const bool need_next = k < j1;
+        load(need_next ? k + 2 : k, R);
+        const int r = row_index(k);
+        if (r == 0 && k != j0 - 1) {
+            // row 0 entered across the periodic seam: its south face is face 0
+            yface(0, Pm, P0, fS);
+            face_mix<1>(fS);
+        }
+        T v[9];
+        advance(r, Pm, P0, Pp, S0, fS, v);     // level 1 of row k
+        ring_put(ring, t & 1, v);
+        if (need_next) cell(R, Pm, Sm);
+        __syncthreads();
+    }
+    __device__ __forceinline__ void produce(int j0, int j1, T *ring) {
+        T PA[9], PB[9], PC[9], SA[9], SB[9], SC[9], fS[9];
+        S R[9], R1[9], R2[9];
+        load(j0 - 2, R);
+        load(j0 - 1, R1);
+        load(j0, R2);
+        cell(R, PA, SA);
+        cell(R1, PB, SB);
+        cell(R2, PC, SC);
+        yface(row_index(j0 - 1), PA, PB, fS);
+        face_mix<1>(fS);
+        int t = 0;
+        for (int k = j0 - 1; k <= j1; k += 3) {
+            produce_row(k, j0, j1, PA, PB, PC, SA, SB, fS, R, ring, t++);
+            if (k + 1 > j1) break;
+            produce_row(k + 1, j0, j1, PB, PC, PA, SB, SC, fS, R, ring, t++);
+            if (k + 2 > j1) break;
+            produce_row(k + 2, j0, j1, PC, PA, PB, SC, SA, fS, R, ring, t++);
+        }
+        __syncthreads();   // the consumer's round for row j1
+    }
+    // consumer, the level-1 row k from the ring: Qm2, Qm1 = level-1 phi rows k-2, k-1; Qk,
+    // Uk receive phi / psi of row k; Um1 = psi row k-1; gS = level-1 y-face values south of
+    // row k-1
+    __device__ __forceinline__ void consume_row(int k, int j0, T (&Qm2)[9], T (&Qm1)[9], T (&Qk)[9], T (&Um1)[9],
+                                                T (&Uk)[9], T (&gS)[9], const T *ring, int t) {
+        T v[9];
+        ring_get(ring, t & 1, v);
+        cell_t(v, Qk, Uk);
+        if (k == j0) {
+            yface(j0, Qm1, Qk, gS);           // level-1 face south of row j0
+            face_mix<1>(gS);
+        } else if (k > j0) {
+            T w[9];
+            advance(k - 1, Qm2, Qm1, Qk, Um1, gS, w);   // level 2 of row k-1
+            store_row(k - 1, w);
+        }
+        __syncthreads();
+    }
+    __device__ __forceinline__ void consume(int j0, int j1, const T *ring) {
+        T QA[9], QB[9], QC[9], UA[9], UB[9], UC[9], gS[9];
+        __syncthreads();   // the producer's round for row j0 - 1
+        int t = 0;
+        for (int k = j0 - 1; k <= j1; k += 3) {
+            consume_row(k, j0, QB, QC, QA, UC, UA, gS, ring, t++);
+            if (k + 1 > j1) break;
+            consume_row(k + 1, j0, QC, QA, QB, UA, UB, gS, ring, t++);
+            if (k + 2 > j1) break;
+            consume_row(k + 2, j0, QA, QB, QC, UB, UC, gS, ring, t++);
+        }
+    }
+
     // the sides of the south face of the mesh (wall, symmetry, wall segment)
     __device__ __forceinline__ void south_sides(T (&fb)[9]) const {
         if (P.bc[SIDE_S] == BC_WALL) bounce<0, -1>(fb, P.bcv[SIDE_S][0], P.bcv[SIDE_S][1], !segS);
@@ -846,6 +951,111 @@ struct March {
             store_row(ny - 1, w);
         }
     }
+
+    // ---- run2b split over a pair of waves (HALO = 2, BND): the producer advances level 0
+    // at rows a .. b with the level-0 ghost rows and lanes and hands each level-1 row to the
+    // consumer through the LDS ring (as produce / consume); the consumer refills the
+    // level-1 ghost lanes, builds the level-1 ghost rows beyond non-periodic y sides and
+    // advances and stores level 1 at rows j0 .. j1 - 1.  Both waves pass b - a + 2
+    // barriers.  Each update is run2b's arithmetic on the same values: the same bits.
+    __device__ __forceinline__ void produce_b(int j0, int j1, T *ring) {
+        const int ny = P.ny;
+        const bool clipS = !per_y && j0 == 0;
+        const bool clipN = !per_y && j1 == ny;
+        const int a = clipS ? 0 : j0 - 1;
+        const int b = clipN ? ny - 1 : j1;
+        const bool ghostS0 = !per_y && a == 0;
+        T Pm[9], P0[9], Pp[9], S0[9], Sp[9], fS[9];
+        S R[9], R1[9], R2[9];
+        load(a - 1, R);
+        load(a, R1);
+        load(a + 1, R2);
+        cell(R1, P0, S0);
+        ghost_x(P0);
+        cell(R2, Pp, Sp);
+        ghost_x(Pp);
+        if (ghostS0) {
+            ghost_y(SIDE_S, P0, Pp, Pm);
+        } else {
+            T Sx[9];
+            cell(R, Pm, Sx);
+            ghost_x(Pm);
+        }
+        yface(row_index(a), Pm, P0, fS);
+        if (ghostS0) south_sides(fS);
+        face_mix<1>(fS);
+        int t = 0;
+        for (int k = a; k <= b; ++k) {
+            load(k + 2, R);   // (the row index wraps, so the load stays in the buffer)
+            const int r = row_index(k);
+            if (per_y && r == 0 && k != a) {
+                yface(0, Pm, P0, fS);
+                face_mix<1>(fS);
+            }
+            T v[9];
+            advance(r, Pm, P0, Pp, S0, fS, v);     // level 1 of row k
+            ring_put(ring, t & 1, v);
+            ++t;
+            if (k + 1 <= b) {
+                copy9(Pm, P0);
+                copy9(P0, Pp);
+                copy9(S0, Sp);
+                if (!per_y && k + 2 == ny) {
+                    ghost_y(SIDE_N, P0, Pm, Pp);
+                } else {
+                    cell(R, Pp, Sp);
+                    ghost_x(Pp);
+                }
+            }
+            __syncthreads();
+        }
+        __syncthreads();   // the consumer's round for row b
+    }
+    __device__ __forceinline__ void consume_b(int j0, int j1, const T *ring) {
+        const int ny = P.ny;
+        const bool clipS = !per_y && j0 == 0;
+        const bool clipN = !per_y && j1 == ny;
+        const int a = clipS ? 0 : j0 - 1;
+        const int b = clipN ? ny - 1 : j1;
+        T Qm2[9], Qm1[9], Q0[9], Um1[9], U0[9], gS[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) Qm1[q] = Q0[q] = U0[q] = gS[q] = (T)0;
+        __syncthreads();   // the producer's round for row a
+        int t = 0;
+        for (int k = a; k <= b; ++k) {
+            T v[9];
+            ring_get(ring, t & 1, v);
+            ++t;
+            copy9(Qm2, Qm1);
+            copy9(Qm1, Q0);
+            copy9(Um1, U0);
+            cell_t(v, Q0, U0);
+            ghost_x(Q0);
+            if (clipS && k == 1) {
+                // level-1 ghost row -1 from rows 0 and 1, then the south face of row 0
+                ghost_y(SIDE_S, Qm1, Q0, Qm2);
+                yface(0, Qm2, Qm1, gS);
+                south_sides(gS);
+                face_mix<1>(gS);
+            } else if (!clipS && k == j0) {
+                yface(j0, Qm1, Q0, gS);           // level-1 face south of row j0
+                face_mix<1>(gS);
+            }
+            if (k - 1 >= j0) {
+                T w[9];
+                advance(k - 1, Qm2, Qm1, Q0, Um1, gS, w);   // level 2 of row k-1
+                store_row(k - 1, w);
+            }
+            __syncthreads();
+        }
+        if (clipN) {
+            // level-1 ghost row ny from rows ny-1 and ny-2, then the update of row ny-1
+            T Qg[9], w[9];
+            ghost_y(SIDE_N, Q0, Qm1, Qg);
+            advance(ny - 1, Qm1, Q0, Qg, U0, gS, w);
+            store_row(ny - 1, w);
+        }
+    }
 };
 
 // Logical block index such that consecutive logical blocks run on one XCD: the
@@ -916,6 +1126,25 @@ __global__ __launch_bounds__(256) void step2_kernel(StepParams<T> P, int parity,
     m.run2(j0, j1);
 }
 
+// Two time steps per launch on a doubly periodic mesh, split over a pair of waves: one
+// workgroup of two waves per work item, wave 0 advancing the first step and wave 1 the
+// second (March::produce / consume), so each holds one level's rows.  Same layout, same
+// work items and the same bits as step2_kernel.
+template <typename T, typename S, int SCHEME>
+__global__ __launch_bounds__(128) void step2p_kernel(StepParams<T> P, int parity, int rows, int nstrips,
+                                                     int nwork) {
+    __shared__ T ring[2 * 9 * 64];
+    const int w = xcd_block();
+    if (w >= nwork) return;   // the whole workgroup: both waves pass the same barriers
+    const int sx = w % nstrips, sy = w / nstrips;
+    const int j0 = sy * rows, j1 = min(P.ny, j0 + rows);
+    const S *src = (const S *)P.buf[parity];
+    S *dst = (S *)P.buf[parity ^ 1];
+    March<T, S, SCHEME, false, 2> m(P, src, dst, P.strip * sx);
+    if (__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) == 0) m.produce(j0, j1, ring);
+    else m.consume(j0, j1, ring);
+}
+
 // Two time steps per launch on a mesh with a non-periodic side (60-column strip layout),
 // parameters by value (the FP64 forms on the DUGKS march). Waves whose columns
 // x0-2 .. x0+61 and rows j0-2 .. j1+1 all lie inside the mesh (or wrap on a periodic axis)
@@ -962,6 +1191,35 @@ __global__ __launch_bounds__(256) void step2b_ptr_kernel(const StepParams<T> *__
     const bool inner_y = m.per_y || (j0 >= 2 && j1 <= P.ny - 2);
     if (inner_x && inner_y) m.run2(j0, j1);
     else m.run2b(j0, j1);
+}
+
+// Two time steps per launch on a mesh with a non-periodic side, split over a pair of waves
+// (one workgroup of two waves per work item; parameters through a device pointer): waves
+// clear of every side take produce / consume, the others produce_b / consume_b.  The same
+// bits as step2b_kernel.
+template <typename T, typename S, int SCHEME>
+__global__ __launch_bounds__(128) void step2bp_kernel(const StepParams<T> *__restrict__ Pp, int parity, int rows,
+                                                      int nstrips, int nwork) {
+    __shared__ T ring[2 * 9 * 64];
+    const StepParams<T> &P = *Pp;
+    const int w = xcd_block();
+    if (w >= nwork) return;   // the whole workgroup: both waves pass the same barriers
+    const int sx = w % nstrips, sy = w / nstrips;
+    const int j0 = sy * rows, j1 = min(P.ny, j0 + rows);
+    const S *src = (const S *)P.buf[parity];
+    S *dst = (S *)P.buf[parity ^ 1];
+    const int x0 = P.strip * sx;
+    March<T, S, SCHEME, true, 2> m(P, src, dst, x0);
+    const bool inner_x = m.per_x || (x0 >= 2 && x0 + 61 <= P.nx - 1);
+    const bool inner_y = m.per_y || (j0 >= 2 && j1 <= P.ny - 2);
+    const bool producer = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) == 0;
+    if (inner_x && inner_y) {
+        if (producer) m.produce(j0, j1, ring);
+        else m.consume(j0, j1, ring);
+    } else {
+        if (producer) m.produce_b(j0, j1, ring);
+        else m.consume_b(j0, j1, ring);
+    }
 }
 
 }  // namespace lbfv

@@ -80,6 +80,7 @@ struct lbfv_ctx {
     bool unstable = false;
     int64_t steps = 0, steps_at_check = 0;
     int rows = 0, wpb = 4;
+    int pairs = 0;                   // two steps per launch, periodic mesh: a pair of waves per item
     // graphs of `gsteps` launches, per scheme (+4 for two steps per launch) and starting buffer
     int gsteps = 32;
     hipGraphExec_t gexec[8][2] = {};
@@ -321,6 +322,22 @@ void *step2_fn(int scheme, bool bnd) {
         else return (void *)step2b_ptr_kernel<T, S, SCHEME_DUGKS>;
     }
     return scheme == SCHEME_BKG ? (void *)step2_kernel<T, S, SCHEME_BKG> : (void *)step2_kernel<T, S, SCHEME_DUGKS>;
+}
+// two steps per launch, a pair of waves per work item (bnd: some side is not periodic;
+// that form reads its parameters through the device copy)
+template <typename T, typename S>
+void *step2p_fn(int scheme, bool bnd) {
+    if (bnd)
+        return scheme == SCHEME_BKG ? (void *)step2bp_kernel<T, S, SCHEME_BKG> : (void *)step2bp_kernel<T, S, SCHEME_DUGKS>;
+    return scheme == SCHEME_BKG ? (void *)step2p_kernel<T, S, SCHEME_BKG> : (void *)step2p_kernel<T, S, SCHEME_DUGKS>;
+}
+void *step2p_fn_variant(int variant, int scheme, bool bnd) {
+    switch (variant) {
+    case V_F64: return step2p_fn<double, double>(scheme, bnd);
+    case V_F32: return step2p_fn<float, float>(scheme, bnd);
+    case V_BF16: return step2p_fn<float, __bf16>(scheme, bnd);
+    default: return step2p_fn<float, _Float16>(scheme, bnd);
+    }
 }
 // two steps per launch; bnd: some side is not periodic
 void *step2_fn_variant(int variant, int scheme, bool bnd) {
@@ -580,10 +597,26 @@ void current_ext(const HostCase &h, double ext[4]) {
     axis_metrics(h.yf, h.periodic_y(), h.dt, h.c, m, ext[SIDE_S], ext[SIDE_N], s);
 }
 
+// a launch of two steps with the pair-of-waves form
+bool paired(const lbfv_ctx *c, bool two) { return two && c->pairs; }
+
 // the step kernel of a launch: two steps per launch (in the 60-column layout; with or
-// without non-periodic sides) or one
-void *launch_fn(const HostCase &h, int scheme, bool two) {
+// without non-periodic sides; one wave or a pair of waves per work item) or one
+void *launch_fn(const lbfv_ctx *c, int scheme, bool two) {
+    const HostCase &h = c->hc;
+    if (paired(c, two)) return step2p_fn_variant(h.variant, scheme, has_boundary(h));
     return two ? step2_fn_variant(h.variant, scheme, has_boundary(h)) : step_fn_variant(h.variant, scheme, has_boundary(h));
+}
+// grid and workgroup of a launch: wpb items of one wave per workgroup, or one item of a
+// pair of waves per workgroup
+void launch_dims(const lbfv_ctx *c, bool two, const StepShape &sh, dim3 &grid, dim3 &block) {
+    if (paired(c, two)) {
+        grid = dim3(sh.nwork);
+        block = dim3(128);
+    } else {
+        grid = dim3(sh.nblocks);
+        block = dim3(64 * sh.wpb);
+    }
 }
 
 // Device copy of the launch parameters for the kernels that take them through a pointer
@@ -631,7 +664,7 @@ int launch_args(lbfv_ctx *c, int scheme, int parity, const double ext[4], bool t
                 StepArgs &a) {
     HostCase &h = c->hc;
     fill_args(h, ext, sh, parity, scheme, a);
-    if (params_by_pointer(h.variant, scheme, has_boundary(h))) {
+    if (params_by_pointer(h.variant, scheme, has_boundary(h)) || (paired(c, two) && has_boundary(h))) {
         const bool f64 = is_f64(h.variant);
         int st = p2b_upload(c, scheme, f64 ? (const void *)&a.pd : (const void *)&a.pf, f64 ? sizeof(a.pd) : sizeof(a.pf),
                             &a.pptr);
@@ -651,7 +684,9 @@ int launch_one(lbfv_ctx *c, int scheme, int parity, const double ext[4], bool tw
     StepArgs a;
     int st = launch_args(c, scheme, parity, ext, two, sh, a);
     if (st) return st;
-    HIPCHK(hipLaunchKernel(launch_fn(h, scheme, two), dim3(sh.nblocks), dim3(64 * sh.wpb), a.args, 0, c->stream));
+    dim3 grid, block;
+    launch_dims(c, two, sh, grid, block);
+    HIPCHK(hipLaunchKernel(launch_fn(c, scheme, two), grid, block, a.args, 0, c->stream));
     return LBFV_OK;
 }
 
@@ -670,9 +705,8 @@ int build_graph(lbfv_ctx *c, int scheme, int parity0, const double ext[4], bool 
         }
         hipKernelNodeParams kp;
         memset(&kp, 0, sizeof(kp));
-        kp.func = launch_fn(h, scheme, two);
-        kp.gridDim = dim3(sh.nblocks);
-        kp.blockDim = dim3(64 * sh.wpb);
+        kp.func = launch_fn(c, scheme, two);
+        launch_dims(c, two, sh, kp.gridDim, kp.blockDim);
         kp.sharedMemBytes = 0;
         kp.kernelParams = a.args;
         kp.extra = nullptr;
@@ -1371,6 +1405,20 @@ int lbfv_get_tile(const lbfv_ctx *c, int32_t *rows, int32_t *wpb) {
     return LBFV_OK;
 }
 
+int lbfv_set_wave_pairs(lbfv_ctx *c, int32_t on) {
+    if (!c) return LBFV_EINVAL;
+    if (on != 0 && on != 1) return c->fail(LBFV_EINVAL, "lbfv_set_wave_pairs: 0 or 1");
+    c->pairs = on;
+    drop_graphs(c);
+    return LBFV_OK;
+}
+
+int lbfv_get_wave_pairs(const lbfv_ctx *c, int32_t *on) {
+    if (!c || !on) return LBFV_EINVAL;
+    *on = c->pairs;
+    return LBFV_OK;
+}
+
 }  // extern "C"
 
 // ====================================================================== autotuner
@@ -1398,7 +1446,7 @@ std::string tune_key(const HostCase &h, int scheme) {
     return s.str();
 }
 
-bool cache_lookup(const char *path, const std::string &key, int &rows, int &wpb, double &ms, int &tb) {
+bool cache_lookup(const char *path, const std::string &key, int &rows, int &wpb, double &ms, int &tb, int &pairs) {
     if (!path) return false;
     std::ifstream in(path);
     std::string line;
@@ -1406,14 +1454,16 @@ bool cache_lookup(const char *path, const std::string &key, int &rows, int &wpb,
     while (std::getline(in, line)) {
         if (line.compare(0, key.size(), key) == 0 && line.size() > key.size() && line[key.size()] == '|') {
             std::istringstream t(line.substr(key.size() + 1));
-            int r, w, k = 1;
+            int r, w, k = 1, pr = 0;
             double m;
             if (t >> r >> w >> m) {
                 if (!(t >> k) || (k != 1 && k != 2)) k = 1;
+                if (!(t >> pr) || (pr != 0 && pr != 1)) pr = 0;
                 rows = r;
                 wpb = w;
                 ms = m;
                 tb = k;
+                pairs = pr;
                 found = true;   // last entry wins
             }
         }
@@ -1421,10 +1471,10 @@ bool cache_lookup(const char *path, const std::string &key, int &rows, int &wpb,
     return found;
 }
 
-void cache_store(const char *path, const std::string &key, int rows, int wpb, double ms, int tb) {
+void cache_store(const char *path, const std::string &key, int rows, int wpb, double ms, int tb, int pairs) {
     if (!path) return;
     std::ofstream out(path, std::ios::app);
-    out << key << "|" << rows << " " << wpb << " " << ms << " " << tb << "\n";
+    out << key << "|" << rows << " " << wpb << " " << ms << " " << tb << " " << pairs << "\n";
 }
 
 }  // namespace
@@ -1439,13 +1489,14 @@ extern "C" int lbfv_autotune(lbfv_ctx *c, int scheme, int32_t trial_steps, const
     const char *path = cache_path ? cache_path : getenv("LBFV_TUNE_CACHE");
     HostCase &h = c->hc;
     const std::string key = tune_key(h, scheme);
-    int rows, wpb, tb;
+    int rows, wpb, tb, pairs;
     double ms;
-    if (cache_lookup(path, key, rows, wpb, ms, tb)) {
+    if (cache_lookup(path, key, rows, wpb, ms, tb, pairs)) {
         int st = lbfv_set_time_block(c, tb);
         if (st) return st;
         c->rows = std::min(rows, h.ny);
         c->wpb = wpb;
+        c->pairs = pairs;
         drop_graphs(c);
         if (best_ms) *best_ms = ms;
         return LBFV_OK;
@@ -1464,30 +1515,39 @@ extern "C" int lbfv_autotune(lbfv_ctx *c, int scheme, int32_t trial_steps, const
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     c->check_every = 0;
-    int best_r = 0, best_w = 0, best_t = 1;
+    int best_r = 0, best_w = 0, best_t = 1, best_p = 0;
+    const int saved_pairs = c->pairs;
     double best = INFINITY;
     int st = LBFV_OK;
-    // candidate shapes: (time block, rows, waves per block)
-    std::vector<std::array<int, 3>> cands;
+    // candidate shapes: (time block, pair of waves per item, rows, waves per block)
+    std::vector<std::array<int, 4>> cands;
     for (int t : {1, 2}) {
         for (int w : {1, 2, 4}) {
             // (1 and 2 rows: more waves for small, latency-bound meshes)
             for (int r : {1, 2, 4, 8, 16, 32, 64, 128, 256})
-                if (r <= h.ny || r == 1) cands.push_back({t, std::min(r, h.ny), w});
+                if (r <= h.ny || r == 1) cands.push_back({t, 0, std::min(r, h.ny), w});
             // balanced heights; the two-step kernel holds more registers (fewer resident
             // waves), so its heights of up to 8 rounds are tried
             void *fn = t == 1 ? step_fn_variant(h.variant, scheme, has_boundary(h))
                               : step2_fn_variant(h.variant, scheme, has_boundary(h));
             for (int r : balanced_rows(h, resident_waves(fn, w), t == 1 ? STRIP1 : STRIP2, t == 1 ? 4 : 8))
-                cands.push_back({t, r, w});
+                cands.push_back({t, 0, r, w});
         }
     }
+    // two steps per launch with a pair of waves per item (one workgroup each); the balanced
+    // heights count resident pairs
+    for (int r : {1, 2, 4, 8, 16, 32, 64, 128, 256})
+        if (r <= h.ny || r == 1) cands.push_back({2, 1, std::min(r, h.ny), 1});
+    for (int r : balanced_rows(h, resident_waves(step2p_fn_variant(h.variant, scheme, has_boundary(h)), 2) / 2,
+                               STRIP2, 8))
+        cands.push_back({2, 1, r, 1});
     std::sort(cands.begin(), cands.end());
     cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
     for (const auto &cand : cands) {
         if ((st = lbfv_set_time_block(c, cand[0]))) break;
-        c->rows = cand[1];
-        c->wpb = cand[2];
+        c->pairs = cand[1];
+        c->rows = cand[2];
+        c->wpb = cand[3];
         drop_graphs(c);
         if ((st = do_steps(c, scheme, 2))) break;   // warm-up
         hipError_t he = hipEventRecord(e0, c->stream);
@@ -1504,8 +1564,9 @@ extern "C" int lbfv_autotune(lbfv_ctx *c, int scheme, int32_t trial_steps, const
         if (per < best) {
             best = per;
             best_t = cand[0];
-            best_r = cand[1];
-            best_w = cand[2];
+            best_p = cand[1];
+            best_r = cand[2];
+            best_w = cand[3];
         }
     }
     // restore the saved state in its own layout, then move it to the chosen one
@@ -1521,13 +1582,15 @@ extern "C" int lbfv_autotune(lbfv_ctx *c, int scheme, int32_t trial_steps, const
     c->steps = saved_steps;
     c->steps_at_check = saved_at;
     c->check_every = saved_check;
+    c->pairs = saved_pairs;
     drop_graphs(c);
     if (st) return st;
     if ((st = lbfv_set_time_block(c, best_t))) return st;
     c->rows = best_r;
     c->wpb = best_w;
+    c->pairs = best_p;
     drop_graphs(c);
-    cache_store(path, key, best_r, best_w, best, best_t);
+    cache_store(path, key, best_r, best_w, best, best_t, best_p);
     if (best_ms) *best_ms = best;
     return LBFV_OK;
 }

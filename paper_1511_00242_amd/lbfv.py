@@ -34,6 +34,7 @@ EXPORTS = (
     "lbfv_init_chapman_enskog", "lbfv_set_f",
     "lbfv_get_f", "lbfv_bind_buffers", "lbfv_required_bytes", "dugks_step", "bkg_step", "lbfv_step",
     "lbfv_moments", "lbfv_totals", "lbfv_totals_device", "lbfv_residual", "lbfv_set_tile", "lbfv_get_tile",
+    "lbfv_set_wave_pairs", "lbfv_get_wave_pairs",
     "lbfv_set_time_block", "lbfv_get_time_block", "lbfv_set_reference_velocity",
     "lbfv_get_reference_velocity",
     "lbfv_autotune", "lbfv_strerror", "lbfv_last_error", "lbfv_batch_create",
@@ -111,6 +112,8 @@ def lib():
             "lbfv_totals_device": ([vp, vp], ip),
             "lbfv_residual": ([vp, dp], ip),
             "lbfv_set_tile": ([vp, C.c_int32, C.c_int32], ip),
+            "lbfv_set_wave_pairs": ([vp, C.c_int32], ip),
+            "lbfv_get_wave_pairs": ([vp, C.POINTER(C.c_int32)], ip),
             "lbfv_set_time_block": ([vp, C.c_int32], ip),
             "lbfv_get_time_block": ([vp, C.POINTER(C.c_int32)], ip),
             "lbfv_set_reference_velocity": ([vp, C.c_double, C.c_double], ip),
@@ -333,6 +336,14 @@ class Context:
         _check(lib().lbfv_get_tile(self.h, C.byref(r), C.byref(w)), self.h)
         return r.value, w.value
 
+    def set_wave_pairs(self, on: bool):
+        _check(lib().lbfv_set_wave_pairs(self.h, int(bool(on))), self.h)
+
+    def get_wave_pairs(self) -> bool:
+        v = C.c_int32()
+        _check(lib().lbfv_get_wave_pairs(self.h, C.byref(v)), self.h)
+        return bool(v.value)
+
     def set_time_block(self, steps: int):
         _check(lib().lbfv_set_time_block(self.h, int(steps)), self.h)
 
@@ -433,6 +444,14 @@ class Batch:
         k, r = C.c_int32(), C.c_int32()
         _check(lib().lbfv_batch_get_shape(self.h, C.byref(k), C.byref(r)), self.h, batch=True)
         return k.value, r.value
+
+    def set_wave_pairs(self, on: bool):
+        _check(lib().lbfv_set_wave_pairs(self.h, int(bool(on))), self.h)
+
+    def get_wave_pairs(self) -> bool:
+        v = C.c_int32()
+        _check(lib().lbfv_get_wave_pairs(self.h, C.byref(v)), self.h)
+        return bool(v.value)
 
     def set_time_block(self, steps: int):
         """Time steps per launch of every case (1 or 2); results are bit-identical."""

@@ -97,6 +97,12 @@ def test_state_errors_before_any_device_work():
     assert L.lib().lbfv_set_time_block(ctx.h, 3) == L.LBFV_EINVAL
     L._check(L.lib().lbfv_set_time_block(ctx.h, 2), ctx.h)      # periodic, no state yet
     L._check(L.lib().lbfv_set_time_block(ctx.h, 1), ctx.h)
+    assert L.lib().lbfv_set_wave_pairs(ctx.h, 2) == L.LBFV_EINVAL
+    assert ctx.get_wave_pairs() is False
+    ctx.set_wave_pairs(True)
+    assert ctx.get_wave_pairs() is True
+    ctx.set_wave_pairs(False)
+    assert L.lib().lbfv_get_wave_pairs(ctx.h, None) == L.LBFV_EINVAL
     # the allocation-free totals need a state (and the mesh metrics on the device)
     assert L.lib().lbfv_totals_device(ctx.h, None) == L.LBFV_EINVAL
     assert L.lib().lbfv_totals_device(None, None) == L.LBFV_EINVAL

@@ -16,7 +16,10 @@
 Bars, each as a relative L2 norm ||X_gpu - X_ref|| / ||X_ref|| over all cells and,
 beside it, as a largest-element ratio max|X_gpu - X_ref| / max|X_ref|:
 FP64 <= 1e-12 on f~ (all nine directions) and on u = (u, v); FP32 deviation storage
-<= 1e-5 on u.  The boundary layer runs at dt/tau = 118, where the FP64 oracle's own
+<= 1e-5 on u.  The FP32 forms round the stored state every step and those roundings
+accumulate as independent errors, whose largest over N values exceeds their root mean
+square by about sqrt(2 ln N) (the extreme of N normal samples): for FP32 the
+largest-element ratio is held to 1e-5 sqrt(2 ln N).  The boundary layer runs at dt/tau = 118, where the FP64 oracle's own
 rounding grows to about 1e-11 over 5,000 steps (it forms f from f~ and Omega from f
 as the paper defines them, which cancels and re-amplifies a few ulp each step): there
 the reference is the extended-precision build of the same oracle source, and the
@@ -62,12 +65,18 @@ def rel_max(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
-def check(label, a, b, tol):
+def max_bar(tol, n, fp32):
+    """the largest-element bar: the norm bar, times sqrt(2 ln N) for the FP32 forms"""
+    return tol * math.sqrt(2.0 * math.log(max(n, 2))) if fp32 else tol
+
+
+def check(label, a, b, tol, fp32=False):
     """Both bars of one comparison, printed, then asserted."""
     e2, em = rel(a, b), rel_max(a, b)
-    print(f"{label}: rel L2 {e2:.2e}, max {em:.2e} (bar {tol:.0e})", flush=True)
+    tm = max_bar(tol, a.size, fp32)
+    print(f"{label}: rel L2 {e2:.2e} (bar {tol:.0e}), max {em:.2e} (bar {tm:.1e})", flush=True)
     assert e2 <= tol, label
-    assert em <= tol, label
+    assert em <= tm, label
 
 
 def velocity(f):
@@ -116,7 +125,7 @@ def test_cavity_256_20000_steps_every_cell(scheme, oscheme):
     # like sqrt(cells)
     assert abs(tot[0] - tot_ref[0]) / tot_ref[0] < max(1e-13, 3e-16 * math.sqrt(w.nx * w.ny))
     g32, _ = run_gpu(w, scheme, n, L.LBFV_FP32, L.LBFV_STORE_DEV_FP32)
-    check(f"cavity256 {n} scheme={scheme} FP32 u", velocity(g32), ref_u, TOL32_U)
+    check(f"cavity256 {n} scheme={scheme} FP32 u", velocity(g32), ref_u, TOL32_U, fp32=True)
 
 
 @pytest.mark.timeout(600)
@@ -150,11 +159,11 @@ def test_boundary_layer_512x256_5000_steps_every_cell(scheme, oscheme):
           f"u {rel(velocity(ref), ext_u):.2e}; GPU vs FP64 oracle: f {rel(g, ref):.2e}", flush=True)
     check(f"bl512 {n} scheme={scheme} FP64 f vs extended", g, ext, TOL64)
     check(f"bl512 {n} scheme={scheme} FP64 u vs extended", velocity(g), ext_u, TOL64)
-    check(f"bl512 {n} scheme={scheme} FP32 (U0 = U_inf) u vs extended", velocity(g32), ext_u, TOL32_U)
+    check(f"bl512 {n} scheme={scheme} FP32 (U0 = U_inf) u vs extended", velocity(g32), ext_u, TOL32_U, fp32=True)
     e2, em = rel(velocity(g32w), ext_u), rel_max(velocity(g32w), ext_u)
+    ok = e2 <= TOL32_U and em <= max_bar(TOL32_U, ext_u.size, True)
     print(f"bl512 {n} scheme={scheme} FP32 (U0 = 0) u vs extended: rel L2 {e2:.2e}, max {em:.2e} "
-          f"({'within' if max(e2, em) <= TOL32_U else 'ABOVE'} the {TOL32_U:.0e} bar; reported only)",
-          flush=True)
+          f"({'within' if ok else 'ABOVE'} the bars; reported only)", flush=True)
     assert np.all(np.isfinite(g32w))
 
 
@@ -165,7 +174,7 @@ def test_boundary_layer_fp32_1000_steps(scheme, oscheme):
     ref_u = velocity(run_oracle(w, oscheme, 1000))
     for u0 in ((0.0, 0.0), (w.meta["u_inf"], 0.0)):
         g, _ = run_gpu(w, scheme, 1000, L.LBFV_FP32, L.LBFV_STORE_DEV_FP32, u0=u0)
-        check(f"bl512 1000 scheme={scheme} FP32 U0={u0} u", velocity(g), ref_u, TOL32_U)
+        check(f"bl512 1000 scheme={scheme} FP32 U0={u0} u", velocity(g), ref_u, TOL32_U, fp32=True)
 
 
 # ------------------------------------------------------------------ Taylor-Green 4096^2, 2000 steps
@@ -191,7 +200,7 @@ def test_tg4096_2000_steps_sampled_cells_against_oracle_fixture():
             check(f"tg4096 {steps} sampled FP64 u", velocity(g), velocity(ref9), TOL64)
             assert abs(tot[0] - totals[0]) / totals[0] < 3e-16 * math.sqrt(w.nx * w.ny)
         else:
-            check(f"tg4096 {steps} sampled FP32 u", velocity(g), velocity(ref9), TOL32_U)
+            check(f"tg4096 {steps} sampled FP32 u", velocity(g), velocity(ref9), TOL32_U, fp32=True)
 
 
 WINDOWS = [(0, 0),            # periodic corner: the window wraps both seams
@@ -242,7 +251,8 @@ def test_tg4096_windows_after_many_steps(scheme, oscheme):
                 check(f"tg4096 window ({jc},{ic}) scheme={scheme} FP64 f", gw, ref, TOL64)
                 check(f"tg4096 window ({jc},{ic}) scheme={scheme} FP64 u", velocity(gw), velocity(ref), TOL64)
             else:
-                check(f"tg4096 window ({jc},{ic}) scheme={scheme} FP32 u", velocity(gw), velocity(ref), TOL32_U)
+                check(f"tg4096 window ({jc},{ic}) scheme={scheme} FP32 u", velocity(gw), velocity(ref), TOL32_U,
+                      fp32=True)
 
 
 def test_tg4096_2000_steps_physics_and_precisions():
@@ -278,7 +288,7 @@ def test_tg4096_2000_steps_physics_and_precisions():
     assert res["fp64"][1] < 1e-13
     for label in ("fp32dev", "bf16dev", "fp16dev"):
         if label == "fp32dev":
-            check("tg4096 2000 steps FP32 u vs GPU FP64", res[label][0], u64, TOL32_U)
+            check("tg4096 2000 steps FP32 u vs GPU FP64", res[label][0], u64, TOL32_U, fp32=True)
         else:
             e = rel(res[label][0], u64)
             print(f"tg4096 2000 steps {label}: u vs GPU FP64 {e:.2e}, mass drift {res[label][1]:.1e}",
@@ -291,18 +301,27 @@ _BATCH = {}
 
 
 def batch96():
-    """The cases, their initial states and the oracle's state after 100 DUGKS steps,
-    computed once for all launch forms."""
+    """The cases, their initial states and the oracle's state after 100 DUGKS steps, in FP64
+    and in extended precision (run side by side), computed once for all launch forms.
+    Most cases run at large dt/tau (up to 920), where the FP64 oracle's own rounding grows
+    past 1e-13 within 100 steps."""
     if not _BATCH:
         cases = I.batch_cases(96, seed=1511)
-        f0s, refs = [], []
-        for w in cases:
-            ora = O.Case(w.xf, w.yf, w.rt, w.tau, w.dt, w.bcs, threads=THREADS)
-            f0 = ora.init_equilibrium(w.rho, w.ux, w.uy)
-            f0s.append(f0)
-            refs.append(ora.run(f0, O.DUGKS, 100))
-        _BATCH.update(cases=cases, f0s=f0s, refs=refs)
-    return _BATCH["cases"], _BATCH["f0s"], _BATCH["refs"]
+        f0s = [O.Case(w.xf, w.yf, w.rt, w.tau, w.dt, w.bcs).init_equilibrium(w.rho, w.ux, w.uy) for w in cases]
+        out = {"fp64": [None] * len(cases), "ext": [None] * len(cases)}
+
+        def run(kind):
+            for i, w in enumerate(cases):
+                ora = O.Case(w.xf, w.yf, w.rt, w.tau, w.dt, w.bcs, threads=max(1, THREADS // 2),
+                             extended=kind == "ext")
+                out[kind][i] = ora.run(f0s[i], O.DUGKS, 100)
+        jobs = [threading.Thread(target=run, args=(k,)) for k in ("fp64", "ext")]
+        for t in jobs:
+            t.start()
+        for t in jobs:
+            t.join()
+        _BATCH.update(cases=cases, f0s=f0s, refs=out["fp64"], exts=out["ext"])
+    return _BATCH["cases"], _BATCH["f0s"], _BATCH["refs"], _BATCH["exts"]
 
 
 @pytest.mark.timeout(600)
@@ -312,8 +331,10 @@ def batch96():
                                                 (L.LBFV_FP32, L.LBFV_STORE_DEV_FP32, "tuned")])
 def test_batch96_every_case(compute, storage, tb):
     """Every one of the 96 cases after one replay of a 100-step graph.  tb "tuned": the
-    launch shape the benchmark times, chosen by the batch autotuner."""
-    cases, f0s, refs = batch96()
+    launch shape the benchmark times, chosen by the batch autotuner.  FP64 is compared with
+    the FP64 oracle where that stays within 1e-13 of the extended-precision oracle, and
+    with the extended-precision oracle elsewhere."""
+    cases, f0s, refs, exts = batch96()
     assert {w.xf.size - 1 for w in cases} == {64, 128, 256, 512}
     b = L.Batch(cases, compute=compute, storage=storage)
     for i, f0 in enumerate(f0s):
@@ -327,17 +348,26 @@ def test_batch96_every_case(compute, storage, tb):
     b.set_shape(graph_steps=100 // tb)
     b.step(L.LBFV_DUGKS, 100)                   # one replay of a 100-step graph
     worst = (0.0, 0.0, -1)
+    n_ext = 0
     for i, w in enumerate(cases):
         g, ref = b.get_f(i), refs[i]
+        if compute == L.LBFV_FP64:
+            e_ora = max(rel(ref, exts[i]), rel_max(ref, exts[i]),
+                        rel(velocity(ref), velocity(exts[i])), rel_max(velocity(ref), velocity(exts[i])))
+            if e_ora > 1e-13:
+                ref = exts[i]
+                n_ext += 1
         gu, ru = velocity(g), velocity(ref)
         eu, emu = rel(gu, ru), rel_max(gu, ru)
         if compute == L.LBFV_FP64:
             ef, emf = rel(g, ref), rel_max(g, ref)
-            assert max(ef, emf, eu, emu) <= TOL64, (i, w.name, ef, emf, eu, emu)
+            assert max(ef, emf, eu, emu) <= TOL64, (i, w.name, w.dt / w.tau, ef, emf, eu, emu)
         else:
-            assert max(eu, emu) <= TOL32_U, (i, w.name, eu, emu)
+            assert eu <= TOL32_U and emu <= max_bar(TOL32_U, gu.size, True), (i, w.name, eu, emu)
         if max(eu, emu) > max(worst[:2]):
             worst = (eu, emu, i)
+    if compute == L.LBFV_FP64:
+        print(f"batch96: {n_ext} of 96 cases against the extended-precision oracle", flush=True)
     print(f"batch96 compute={compute} tb={tb}: all 96 cases within the bar; largest u error "
           f"(case {worst[2]}, {cases[worst[2]].name}): rel L2 {worst[0]:.2e}, max {worst[1]:.2e}", flush=True)
     b.close()
