@@ -109,6 +109,45 @@ template <> struct Storage<_Float16> {
     __device__ __forceinline__ static _Float16 store(float v, int a) { return (_Float16)(v * (float)inv_wgt(a)); }
 };
 
+// ---------------------------------------------------------------- row loads and stores
+// Each direction's slice of a row is one buffer (resource built in scalar registers from
+// the row's wave-uniform address, range = the padded row) and each lane reads or writes at
+// its own 32-bit byte offset: no 64-bit address arithmetic in the vector unit, and an
+// offset past the row reads 0 / writes nothing instead of reaching other memory.
+constexpr int kBufWord3 = 0x00020000;   // raw (unformatted) buffer, GFX9 family
+template <typename S> struct BufIO;
+template <> struct BufIO<double> {
+    __device__ __forceinline__ static double load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    }
+    __device__ __forceinline__ static void store(double v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+        typedef unsigned u2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, off, 0, 2);   // 2: nt
+    }
+};
+template <> struct BufIO<float> {
+    __device__ __forceinline__ static float load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    }
+    __device__ __forceinline__ static void store(float v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 2);
+    }
+};
+template <typename H> struct BufIO16 {
+    __device__ __forceinline__ static H load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+        return __builtin_bit_cast(H, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+    }
+    __device__ __forceinline__ static void store(H v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, off, 0, 2);
+    }
+};
+template <> struct BufIO<__bf16> : BufIO16<__bf16> {};
+template <> struct BufIO<_Float16> : BufIO16<_Float16> {};
+template <typename S>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_buffer(const S *row, int64_t pitch) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)row, (short)0, (int)(pitch * (int64_t)sizeof(S)), kBufWord3);
+}
+
 // ---------------------------------------------------------------- uniform reads
 // Row metrics are the same for the whole wave.  Reading them through the constant
 // address space makes them scalar loads (counted by lgkmcnt): as vector loads they would
@@ -306,7 +345,7 @@ struct March {
     S *__restrict__ dst;
     int lane, col;
     int ccol;                  // column this lane loads (wrapped / clamped)
-    int64_t lslot, sslot;      // storage slot this lane loads / stores
+    uint32_t lbyte, sbyte;     // byte offset, within its row, of the slot this lane loads / stores
     bool per_x, per_y;
     bool ghostW, ghostE;       // this wave holds the west / east ghost column
     bool segS, segN;           // this lane's column lies in the south / north wall segment
@@ -327,11 +366,11 @@ struct March {
         else ccol = col < 0 ? 0 : (col >= nx ? nx - 1 : col);
         if (ccol >= nx) ccol = nx - 1;   // garbage lanes past a short periodic row
         if (ccol < 0) ccol = 0;
-        lslot = col_slot(ccol, P.strip);
+        lbyte = (uint32_t)(col_slot(ccol, P.strip) * (int64_t)sizeof(S));
         // the output lanes HALO..HALO+strip-1 own slots 0..strip-1 of this strip's block and
         // the remaining lanes the pad slots: the wave writes its 64-slot block whole (pad
         // values are never read)
-        sslot = (int64_t)(x0 / P.strip) * SLOTS + ((lane - HALO) & (SLOTS - 1));
+        sbyte = (uint32_t)(((x0 / P.strip) * SLOTS + ((lane - HALO) & (SLOTS - 1))) * (int)sizeof(S));
         ghostW = BND && !per_x && x0 == 0;
         segS = BND && P.wfrom[SIDE_S] >= 0 && col >= P.wfrom[SIDE_S];
         segN = BND && P.wfrom[SIDE_N] >= 0 && col >= P.wfrom[SIDE_N];
@@ -374,9 +413,9 @@ struct March {
         return r < 0 ? r + ny : (r >= ny ? r - ny : r);
     }
     __device__ __forceinline__ void load(int r, S (&raw)[9]) const {
-        const S *p = src + (int64_t)row_index(r) * P.pitch + lslot;
+        const S *row = src + (int64_t)row_index(r) * P.pitch;
 #pragma unroll
-        for (int a = 0; a < 9; ++a) raw[a] = p[a * P.plane];
+        for (int a = 0; a < 9; ++a) raw[a] = BufIO<S>::load(row_buffer(row + a * P.plane, P.pitch), lbyte);
     }
     // phi (and psi for DUGKS) of one row from its stored values.  Sec. 2.2: psi =
     // f~+ = x + cd (dfeq - x); f-bar+ = x + cb (dfeq - x) (closed forms after eliminating
@@ -588,11 +627,11 @@ struct March {
     }
 
     __device__ __forceinline__ void store_row(int r, const T (&v)[9]) const {
-        S *out = dst + (int64_t)r * P.pitch + sslot;
+        S *out = dst + (int64_t)r * P.pitch;
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
             // streaming store: the new state is not read again within this step
-            __builtin_nontemporal_store(Storage<S>::store(v[a], a), out + a * P.plane);
+            BufIO<S>::store(Storage<S>::store(v[a], a), row_buffer(out + a * P.plane, P.pitch), sbyte);
         }
     }
 

@@ -43,8 +43,9 @@ import make_long_horizon as G   # noqa: E402
 pytestmark = pytest.mark.gpu
 TOL64 = 1e-12
 TOL32_U = 1e-5
-BENCH_TILE = (142, 2)            # the timed 4096^2 launch shape: rows, waves per block,
-BENCH_TB = 2                    # and two steps per launch
+BENCH_TILE = (142, 1)            # the timed 4096^2 launch shape: rows, waves per block,
+BENCH_TB = 2                    # two steps per launch,
+BENCH_PAIRS = True              # a pair of waves per work item
 THREADS = min(16, int(os.environ.get("LBFV_ORACLE_THREADS", os.environ.get("OMP_NUM_THREADS", "8"))))
 XX, XY, _W, _REV = O.model()
 
@@ -192,6 +193,7 @@ def test_tg4096_2000_steps_sampled_cells_against_oracle_fixture():
             ctx.set_time_block(BENCH_TB)
             if label == "fp64":
                 ctx.set_tile(*BENCH_TILE)
+                ctx.set_wave_pairs(BENCH_PAIRS)
             ctx.dugks_step(steps)
             tot = ctx.totals()
             g = ctx.get_f()[:, jj, ii]
@@ -239,6 +241,7 @@ def test_tg4096_windows_after_many_steps(scheme, oscheme):
             ctx.set_time_block(BENCH_TB)
             if tile:
                 ctx.set_tile(*tile)
+                ctx.set_wave_pairs(BENCH_PAIRS)
             ctx.step(scheme, K_WIN)
             outs[label] = ctx.get_f()
     for (jc, ic) in WINDOWS:
@@ -275,6 +278,7 @@ def test_tg4096_2000_steps_physics_and_precisions():
             ctx.set_time_block(BENCH_TB)
             if label == "fp64":
                 ctx.set_tile(*BENCH_TILE)
+                ctx.set_wave_pairs(BENCH_PAIRS)
             ctx.dugks_step(n)
             m1 = ctx.totals()[0]
             _, ux, uy = ctx.moments()
