@@ -53,7 +53,7 @@ def parse():
     p.add_argument("--only", default="", help="comma list of variant names to run")
     p.add_argument("--tile", default="", help="rows,waves_per_block for every run (skips the autotuner)")
     p.add_argument("--batch-shape", default="",
-                   help="time_block,rows,wave_per_item (0/1) of the batch (skips its autotuner)")
+                   help="time_block,rows,wave_per_item[,wave_pairs] (0/1) of the batch (skips its autotuner)")
     p.add_argument("--time-block", type=int, default=HEADLINE_TIME_BLOCK,
                    help="steps per launch with --tile on doubly periodic meshes (1 or 2)")
     p.add_argument("--pairs", type=int, default=HEADLINE_PAIRS,
@@ -181,15 +181,18 @@ def run_batch(steps, warmup, stream, shape=""):
     for i, w in enumerate(cases):
         b.init_equilibrium(i, w.rho, w.ux, w.uy)
     if shape:
-        tb, rows, per_item = (int(x) for x in shape.split(","))
+        parts = [int(x) for x in shape.split(",")]
+        tb, rows, per_item = parts[:3]
         b.set_time_block(tb)
         b.set_shape(rows=rows)
         b.set_grid_form(per_item)
+        b.set_wave_pairs(parts[3] if len(parts) > 3 else 0)
     else:
         b.autotune(L.LBFV_DUGKS, 20)          # time block, row-block height, grid (state kept)
     graph_steps, rows = b.get_shape()
     tb = b.get_time_block()
     per_item = b.get_grid_form()
+    pairs = b.get_wave_pairs()
     cells, items = b.info()
     b.step(L.LBFV_DUGKS, warmup)
     torch.cuda.synchronize()
@@ -219,7 +222,8 @@ def run_batch(steps, warmup, stream, shape=""):
             t_seq[label] += e0.elapsed_time(e1) / 32
             ctx.close()
     return dict(name="batch96_dugks_fp32dev", cases=len(cases), cells=cells, work_items=items, rows=rows,
-                graph_launches=graph_steps, time_block=tb, grid="wave_per_item" if per_item else "resident_waves",
+                graph_launches=graph_steps, time_block=tb, wave_pairs=int(pairs),
+                grid="wave_per_item" if per_item else "resident_waves",
                 ms_per_step=ms, mlups=cells / (ms * 1e-3) / 1e6, alg_gbs=cells * BYTES["f32"] / (ms * 1e-3) / 1e9,
                 alg_frac_of_hbm_peak=cells * BYTES["f32"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                 seq_fp64_ms_per_step=t_seq["fp64"], speedup_vs_seq_fp64=t_seq["fp64"] / ms,
@@ -589,7 +593,8 @@ def main():
         for name, sch, comp, sto, dt in specs:
             if only and name not in only:
                 continue
-            r = run_single(name, w, sch, comp, sto, steps, a.warmup, a.check_every, stream, tile, a.time_block)
+            r = run_single(name, w, sch, comp, sto, steps, a.warmup, a.check_every, stream, tile, a.time_block,
+                           pairs=a.pairs)
             # bytes the method defines per step over the time per step; with two steps per
             # launch the state is read and written once per two steps, so this can pass the
             # HBM peak
@@ -624,7 +629,7 @@ def main():
                 continue
             # microseconds per step: at least 2000 timed steps (tens of milliseconds)
             r = run_single(name, ws, sch, L.LBFV_FP64, L.LBFV_STORE_NATIVE, max(10 * steps, 2000),
-                           max(a.warmup, 200), a.check_every * 10, stream, tile, a.time_block)
+                           max(a.warmup, 200), a.check_every * 10, stream, tile, a.time_block, pairs=a.pairs)
             variants[name] = r
             print(f"[bench] {name}: {r['ms_per_step'] * 1e3:.2f} us/step {r['mlups']:.0f} MLUPS", file=sys.stderr,
                   flush=True)

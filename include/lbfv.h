@@ -266,6 +266,12 @@ int lbfv_batch_get_shape(const lbfv_batch *b, int32_t *graph_steps, int32_t *row
  * EINVAL for another value. */
 int lbfv_batch_set_grid_form(lbfv_batch *b, int32_t wave_per_item);
 int lbfv_batch_get_grid_form(const lbfv_batch *b, int32_t *wave_per_item);
+/* Work split of two steps per launch in the batch, as lbfv_set_wave_pairs for one case:
+ * 1 gives each work item a workgroup of two wavefronts, one per step level; the grid form
+ * then counts pairs instead of waves.  The same bits either way; ignored with one step per
+ * launch.  EINVAL unless 0 or 1. */
+int lbfv_batch_set_wave_pairs(lbfv_batch *b, int32_t on);
+int lbfv_batch_get_wave_pairs(const lbfv_batch *b, int32_t *on);
 /* Time steps per launch of the batch: 1 (default) or 2, as lbfv_set_time_block for one
  * case: with 2 every case moves to the 60-column strip layout, each launch advances every
  * case by two steps with the intermediate step in registers, a graph of K launches by 2K

@@ -61,4 +61,35 @@ __global__ __launch_bounds__(256) void batch2_kernel(const StepParams<T> *__rest
     }
 }
 
+// Two time steps per launch of the batched form split over a pair of waves per work item
+// (a workgroup of two waves; as step2p_kernel / step2bp_kernel): the workgroup walks the
+// work list with a grid stride, both waves taking the same items, so both pass the same
+// barriers.  The same bits as batch2_kernel.
+template <typename T, typename S, int SCHEME, bool BND>
+__global__ __launch_bounds__(128) void batch2p_kernel(const StepParams<T> *__restrict__ cases,
+                                                      const BatchItem *__restrict__ items, int nitems,
+                                                      int parity) {
+    __shared__ T ring[2 * 9 * 64];
+    const bool producer = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) == 0;
+    for (int w = xcd_block(); w < nitems; w += gridDim.x) {
+        const BatchItem it = items[w];
+        const StepParams<T> &P = cases[it.c];
+        const S *src = (const S *)P.buf[parity];
+        S *dst = (S *)P.buf[parity ^ 1];
+        March<T, S, SCHEME, BND, 2> m(P, src, dst, it.x0);
+        bool inner = true;
+        if constexpr (BND) {
+            inner = (m.per_x || (it.x0 >= 2 && it.x0 + 61 <= P.nx - 1)) &&
+                    (m.per_y || (it.j0 >= 2 && it.j1 <= P.ny - 2));
+        }
+        if (inner) {
+            if (producer) m.produce(it.j0, it.j1, ring);
+            else m.consume(it.j0, it.j1, ring);
+        } else {
+            if (producer) m.produce_b(it.j0, it.j1, ring);
+            else m.consume_b(it.j0, it.j1, ring);
+        }
+    }
+}
+
 }  // namespace lbfv

@@ -116,8 +116,10 @@ struct lbfv_batch {
     int parity = 0;                  // all cases share the step parity
     int tblock = 1;                  // time steps per launch (1 or 2; 2: 60-column strips)
     bool wave_per_item = false;      // grid of one wave per work item instead of the resident waves
+    bool pairs = false;              // two steps per launch: a pair of waves per work item
     bool bnd = false;                // some case has a non-periodic side
-    int slots[2][2] = {{0, 0}, {0, 0}};   // resident waves of the batch kernels, per time block and scheme
+    int slots[3][2] = {{0, 0}, {0, 0}, {0, 0}};   // resident work items of the batch kernels: one step, two
+                                                   // steps, two steps with pairs of waves; per scheme
     hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     bool has_state = false;
     std::string last_error;
@@ -358,7 +360,10 @@ void *step_fn_variant(int variant, int scheme, bool bnd) {
     }
 }
 template <typename T, typename S, bool BND>
-void *batch_fn_b(int scheme, bool two) {
+void *batch_fn_b(int scheme, bool two, bool pairs) {
+    if (two && pairs)
+        return scheme == SCHEME_DUGKS ? (void *)batch2p_kernel<T, S, SCHEME_DUGKS, BND>
+                                      : (void *)batch2p_kernel<T, S, SCHEME_BKG, BND>;
     if (two)
         return scheme == SCHEME_DUGKS ? (void *)batch2_kernel<T, S, SCHEME_DUGKS, BND>
                                       : (void *)batch2_kernel<T, S, SCHEME_BKG, BND>;
@@ -366,16 +371,17 @@ void *batch_fn_b(int scheme, bool two) {
                                   : (void *)batch_kernel<T, S, SCHEME_BKG, BND>;
 }
 template <typename T, typename S>
-void *batch_fn(int scheme, bool bnd, bool two) {
-    return bnd ? batch_fn_b<T, S, true>(scheme, two) : batch_fn_b<T, S, false>(scheme, two);
+void *batch_fn(int scheme, bool bnd, bool two, bool pairs) {
+    return bnd ? batch_fn_b<T, S, true>(scheme, two, pairs) : batch_fn_b<T, S, false>(scheme, two, pairs);
 }
-// two: two time steps per launch (the cases in the 60-column strip layout)
-void *batch_fn_variant(int variant, int scheme, bool bnd, bool two) {
+// two: two time steps per launch (the cases in the 60-column strip layout); pairs: with a
+// pair of waves per work item
+void *batch_fn_variant(int variant, int scheme, bool bnd, bool two, bool pairs = false) {
     switch (variant) {
-    case V_F64: return batch_fn<double, double>(scheme, bnd, two);
-    case V_F32: return batch_fn<float, float>(scheme, bnd, two);
-    case V_BF16: return batch_fn<float, __bf16>(scheme, bnd, two);
-    default: return batch_fn<float, _Float16>(scheme, bnd, two);
+    case V_F64: return batch_fn<double, double>(scheme, bnd, two, pairs);
+    case V_F32: return batch_fn<float, float>(scheme, bnd, two, pairs);
+    case V_BF16: return batch_fn<float, __bf16>(scheme, bnd, two, pairs);
+    default: return batch_fn<float, _Float16>(scheme, bnd, two, pairs);
     }
 }
 
@@ -1664,24 +1670,35 @@ struct BatchArgs {
     }
 };
 
-// resident waves of the batch kernel (from its occupancy)
+bool batch_paired(const lbfv_batch *b, bool two) { return two && b->pairs; }
+
+// work items the batch kernel keeps resident on the device (from its occupancy): one per
+// wave, or one per pair of waves
 int batch_slots(lbfv_batch *b, int scheme, bool two) {
-    int &slots = b->slots[two ? 1 : 0][scheme];
+    const bool pr = batch_paired(b, two);
+    int &slots = b->slots[pr ? 2 : (two ? 1 : 0)][scheme];
     if (slots <= 0) {
-        slots = resident_waves(batch_fn_variant(b->variant, scheme, b->bnd, two), 4);
-        if (slots <= 0) slots = 256 * 8;
+        slots = pr ? resident_waves(batch_fn_variant(b->variant, scheme, b->bnd, two, true), 2) / 2
+                   : resident_waves(batch_fn_variant(b->variant, scheme, b->bnd, two), 4);
+        if (slots <= 0) slots = 256 * 4;
     }
     return slots;
 }
 
-// Persistent grid: exactly the blocks of 4 waves that fit on the device at once, capped
-// by the work list; or one wave per item, so that the hardware hands a freed slot the next
-// block (items of uneven cost then balance themselves).
+// Persistent grid: exactly the workgroups that fit on the device at once (4 waves, or one
+// pair of waves), capped by the work list; or one item per wave (per pair), so that the
+// hardware hands a freed slot the next workgroup (items of uneven cost then balance
+// themselves).
 int batch_grid(lbfv_batch *b, int scheme, bool two) {
+    if (batch_paired(b, two)) {
+        const int all = std::max(1, b->nitems);
+        return b->wave_per_item ? all : std::min(all, batch_slots(b, scheme, two));
+    }
     const int all = std::max(1, (b->nitems + 3) / 4);
     if (b->wave_per_item) return all;
     return std::min(all, batch_slots(b, scheme, two) / 4);
 }
+int batch_block(const lbfv_batch *b, bool two) { return batch_paired(b, two) ? 128 : 256; }
 
 // Row-block heights in 2 ... 64 that a cost model ranks best for the batch: whole rounds
 // of the resident waves times the rows each item marches (its rows plus the rows the
@@ -1704,8 +1721,8 @@ std::vector<int> batch_balanced_rows(const lbfv_batch *b, int slots, int count) 
 int batch_launch_one(lbfv_batch *b, int scheme, int parity, bool two = false) {
     BatchArgs a{b->d_params, b->d_items, b->nitems, parity};
     a.bind();
-    hipError_t e = hipLaunchKernel(batch_fn_variant(b->variant, scheme, b->bnd, two), dim3(batch_grid(b, scheme, two)),
-                                   dim3(256), a.args, 0, b->stream);
+    hipError_t e = hipLaunchKernel(batch_fn_variant(b->variant, scheme, b->bnd, two, batch_paired(b, two)),
+                                   dim3(batch_grid(b, scheme, two)), dim3(batch_block(b, two)), a.args, 0, b->stream);
     if (e != hipSuccess) return b->fail(LBFV_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
     return LBFV_OK;
 }
@@ -1721,9 +1738,9 @@ int batch_build_graph(lbfv_batch *b, int scheme, int parity0) {
         a.bind();
         hipKernelNodeParams kp;
         memset(&kp, 0, sizeof(kp));
-        kp.func = batch_fn_variant(b->variant, scheme, b->bnd, two);
+        kp.func = batch_fn_variant(b->variant, scheme, b->bnd, two, batch_paired(b, two));
         kp.gridDim = dim3(batch_grid(b, scheme, two));
-        kp.blockDim = dim3(256);
+        kp.blockDim = dim3(batch_block(b, two));
         kp.kernelParams = a.args;
         hipGraphNode_t node;
         hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
@@ -1882,6 +1899,22 @@ int lbfv_batch_get_grid_form(const lbfv_batch *b, int32_t *wave_per_item) {
     return LBFV_OK;
 }
 
+int lbfv_batch_set_wave_pairs(lbfv_batch *b, int32_t on) {
+    if (!b) return LBFV_EINVAL;
+    if (on != 0 && on != 1) return b->fail(LBFV_EINVAL, "lbfv_batch_set_wave_pairs: 0 or 1");
+    if ((bool)on != b->pairs) {
+        b->pairs = on;
+        batch_drop_graphs(b);
+    }
+    return LBFV_OK;
+}
+
+int lbfv_batch_get_wave_pairs(const lbfv_batch *b, int32_t *on) {
+    if (!b || !on) return LBFV_EINVAL;
+    *on = b->pairs ? 1 : 0;
+    return LBFV_OK;
+}
+
 int lbfv_batch_set_time_block(lbfv_batch *b, int32_t steps) {
     if (!b) return LBFV_EINVAL;
     if (steps != 1 && steps != 2) return b->fail(LBFV_EINVAL, "lbfv_batch_set_time_block: steps must be 1 or 2");
@@ -1922,7 +1955,7 @@ int lbfv_batch_autotune(lbfv_batch *b, int scheme, int32_t trial_steps, double *
         return b->fail(LBFV_ENOMEM, "batch autotune: cannot allocate the state copy");
     }
     const int parity0 = b->parity, rows0 = b->rows, gsteps0 = b->gsteps, tb0 = b->tblock;
-    const bool wpi0 = b->wave_per_item;
+    const bool wpi0 = b->wave_per_item, pairs0 = b->pairs;
     hipError_t e = hipSuccess;
     size_t off = 0;
     for (const auto &h : b->cases) {
@@ -1940,10 +1973,13 @@ int lbfv_batch_autotune(lbfv_batch *b, int scheme, int32_t trial_steps, double *
     // one graph); the trials advance the state, which is put back below
     const int ts = trial_steps + (trial_steps & 1);
     int best_rows = rows0, best_tb = tb0;
-    bool best_wpi = wpi0;
+    bool best_wpi = wpi0, best_pairs = pairs0;
     double best = INFINITY;
     b->gsteps = ts;
-    for (int tb : {1, 2}) {
+    // (time block, pair of waves per item): one step; two steps with one wave or a pair
+    for (auto form : std::vector<std::pair<int, bool>>{{1, false}, {2, false}, {2, true}}) {
+        const int tb = form.first;
+        b->pairs = form.second;
         if (st || (st = lbfv_batch_set_time_block(b, tb))) break;
         std::vector<int> heights = {2, 4, 8, 16, 32, 64};
         for (int r : batch_balanced_rows(b, batch_slots(b, scheme, tb == 2), 3))
@@ -1969,6 +2005,7 @@ int lbfv_batch_autotune(lbfv_batch *b, int scheme, int32_t trial_steps, double *
                 best_rows = r;
                 best_tb = tb;
                 best_wpi = b->wave_per_item;
+                best_pairs = b->pairs;
             }
         }
     }
@@ -1978,6 +2015,7 @@ int lbfv_batch_autotune(lbfv_batch *b, int scheme, int32_t trial_steps, double *
     b->gsteps = gsteps0;
     b->tblock = tb0;
     b->wave_per_item = st ? wpi0 : best_wpi;
+    b->pairs = st ? pairs0 : best_pairs;
     for (auto &h : b->cases) h.set_strip(tb0 == 2 ? STRIP2 : STRIP1);
     b->rows = st ? rows0 : best_rows;
     int st2 = is_f64(b->variant) ? batch_upload_params<double>(b) : batch_upload_params<float>(b);

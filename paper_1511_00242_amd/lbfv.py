@@ -42,7 +42,7 @@ EXPORTS = (
     "lbfv_batch_moments", "lbfv_batch_nonfinite", "lbfv_batch_set_shape", "lbfv_batch_info",
     "lbfv_batch_get_shape", "lbfv_batch_autotune", "lbfv_batch_last_error",
     "lbfv_batch_set_time_block", "lbfv_batch_get_time_block", "lbfv_batch_set_grid_form",
-    "lbfv_batch_get_grid_form",
+    "lbfv_batch_get_grid_form", "lbfv_batch_set_wave_pairs", "lbfv_batch_get_wave_pairs",
     "lbfv_batch_destroy",
 )
 
@@ -138,6 +138,8 @@ def lib():
             "lbfv_batch_get_time_block": ([vp, C.POINTER(C.c_int32)], ip),
             "lbfv_batch_set_grid_form": ([vp, C.c_int32], ip),
             "lbfv_batch_get_grid_form": ([vp, C.POINTER(C.c_int32)], ip),
+            "lbfv_batch_set_wave_pairs": ([vp, C.c_int32], ip),
+            "lbfv_batch_get_wave_pairs": ([vp, C.POINTER(C.c_int32)], ip),
             "lbfv_batch_info": ([vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)], ip),
             "lbfv_batch_destroy": ([vp], ip),
         }
@@ -470,6 +472,14 @@ class Batch:
         t = C.c_int32()
         _check(lib().lbfv_batch_get_grid_form(self.h, C.byref(t)), self.h, batch=True)
         return bool(t.value)
+
+    def set_wave_pairs(self, on: bool):
+        _check(lib().lbfv_batch_set_wave_pairs(self.h, int(bool(on))), self.h, batch=True)
+
+    def get_wave_pairs(self) -> bool:
+        v = C.c_int32()
+        _check(lib().lbfv_batch_get_wave_pairs(self.h, C.byref(v)), self.h, batch=True)
+        return bool(v.value)
 
     def autotune(self, scheme: int, trial_steps: int = 20) -> float:
         """Pick the time block and the work list's row-block height by timing; the state is

@@ -404,16 +404,19 @@ def test_batch_two_steps_per_launch_equal_one(compute, storage, scheme):
     """lbfv_batch_set_time_block(2): the same bits as one step per launch on every case,
     through graph replays, two-step launches, an odd last step and switches of the time
     block with a state in flight (each switch moves the state between strip layouts), with
-    the two grid forms.  With 16-bit storage the intermediate step of a two-step launch is not rounded to 16
-    bits: there both results are compared with the oracle instead."""
+    the two grid forms and with one wave or a pair of waves per work item.  With 16-bit
+    storage the intermediate step of a two-step launch is not rounded to 16 bits: there
+    the one- and two-step results are compared with the oracle instead."""
     cases = _batch_sides_mix()
     f0s = [perturbed_state(oracle_case(w, 1), w, 40 + i) for i, w in enumerate(cases)]
     outs = []
-    for tb in (1, 2):
+    for tb, pairs, per_item in ((1, False, False), (2, False, True), (2, True, False), (2, True, True)):
         b = L.Batch(cases, compute=compute, storage=storage)
         b.set_shape(graph_steps=4, rows=8)
-        b.set_grid_form(tb == 2)          # the two-step run also takes the other grid form
-        assert b.get_grid_form() == (tb == 2)
+        b.set_grid_form(per_item)
+        assert b.get_grid_form() == per_item
+        b.set_wave_pairs(pairs)
+        assert b.get_wave_pairs() == pairs
         for i, f0 in enumerate(f0s):
             b.set_f(i, f0)
         b.step(scheme, 3)
@@ -426,8 +429,10 @@ def test_batch_two_steps_per_launch_equal_one(compute, storage, scheme):
         b.step(scheme, 3)
         outs.append([b.get_f(i) for i in range(len(cases))])
         b.close()
-    for i, (a, c) in enumerate(zip(*outs)):
+    for i, (a, c, d, e) in enumerate(zip(*outs)):
         assert np.all(np.isfinite(a)), cases[i].name
+        # the pair form gives the bits of the one-wave form in every storage
+        assert np.array_equal(c, d) and np.array_equal(c, e), (cases[i].name, "pairs")
         if storage != L.LBFV_STORE_DEV_BF16:
             assert np.array_equal(a, c), (cases[i].name, rel(c, a))
             continue
