@@ -278,6 +278,7 @@ def cavity_residual(a, stream):
     if a.save:
         np.save(a.save, ctx.get_f())
     rows, wpb = ctx.get_tile()
+    tb, pairs = ctx.get_time_block(), ctx.get_wave_pairs()
     ctx.close()
     cells = 256 * 256
     return {"workload": "cavity_256x256_tanh_re1000", "scheme": a.scheme, "precision": a.precision,
@@ -285,7 +286,7 @@ def cavity_residual(a, stream):
             "steps": steps, "lid_transits": steps * w.dt * 0.1, "residual": res, "target": a.target,
             "reached": res < a.target, "gpu_s": gpu_ms / 1e3,
             "mlups": cells * 50000 * len(hist) / (gpu_ms * 1e-3) / 1e6 if gpu_ms else None,
-            "mass_rel_drift": abs(m1 - m0) / m0, "tile": [rows, wpb],
+            "mass_rel_drift": abs(m1 - m0) / m0, "tile": [rows, wpb], "time_block": tb, "wave_pairs": int(pairs),
             "history": [[s_, r_] for s_, r_ in hist[:: max(1, len(hist) // 40)]] + [[steps, res]]}
 
 
