@@ -34,9 +34,9 @@ __global__ __launch_bounds__(256) void batch_kernel(const StepParams<T> *__restr
 }
 
 // Two time steps per launch of the batched form (every case in the 60-column strip
-// layout): a wave whose strip and row block need no ghost cells takes the periodic
-// march, the others the march with level-1 ghost rows and lanes, as in the single-case
-// two-step kernel.
+// layout): a wave whose row block needs no ghost rows takes the rotating march (x-side
+// ghost lanes refilled where the strip has them), the others the march with level-1 ghost
+// rows, as in the single-case two-step kernel.
 template <typename T, typename S, int SCHEME, bool BND>
 __global__ __launch_bounds__(256) void batch2_kernel(const StepParams<T> *__restrict__ cases,
                                                      const BatchItem *__restrict__ items, int nitems,
@@ -51,9 +51,8 @@ __global__ __launch_bounds__(256) void batch2_kernel(const StepParams<T> *__rest
         S *dst = (S *)P.buf[parity ^ 1];
         March<T, S, SCHEME, BND, 2> m(P, src, dst, it.x0);
         if constexpr (BND) {
-            const bool inner_x = m.per_x || (it.x0 >= 2 && it.x0 + 61 <= P.nx - 1);
             const bool inner_y = m.per_y || (it.j0 >= 2 && it.j1 <= P.ny - 2);
-            if (inner_x && inner_y) m.run2(it.j0, it.j1);
+            if (inner_y) m.run2(it.j0, it.j1);
             else m.run2b(it.j0, it.j1);
         } else {
             m.run2(it.j0, it.j1);
@@ -78,10 +77,7 @@ __global__ __launch_bounds__(128) void batch2p_kernel(const StepParams<T> *__res
         S *dst = (S *)P.buf[parity ^ 1];
         March<T, S, SCHEME, BND, 2> m(P, src, dst, it.x0);
         bool inner = true;
-        if constexpr (BND) {
-            inner = (m.per_x || (it.x0 >= 2 && it.x0 + 61 <= P.nx - 1)) &&
-                    (m.per_y || (it.j0 >= 2 && it.j1 <= P.ny - 2));
-        }
+        if constexpr (BND) inner = m.per_y || (it.j0 >= 2 && it.j1 <= P.ny - 2);
         if (inner) {
             if (producer) m.produce(it.j0, it.j1, ring);
             else m.consume(it.j0, it.j1, ring);

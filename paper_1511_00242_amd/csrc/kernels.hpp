@@ -65,6 +65,8 @@ struct StepParams {
     T wsv[4][2];            // that segment's 6 U_w / c
     int32_t strip;          // output columns per 64-slot storage block (62, or 60 for two steps per pass)
     T ext[4];               // linear ghost extrapolation factor per side
+    T gext[4];              // the ghost rule's factor: ext, or 0 on a zero-order outflow side
+    T gin[4][9];            // inflow side: ghost deviation feq_a(rho, u) - F_a, per direction
     T rho0;                 // deviation reference density (0: plain storage)
     T m0x, m0y;             // reference momentum rho0 U0 / c of the deviation storage (FP32 only)
     T q0[9];                // rho0 (4.5 (e_a.U0/c)^2 - 1.5 |U0/c|^2), the reference's second-order part
@@ -181,8 +183,12 @@ __device__ __forceinline__ double shl1(double v) {
 }
 
 // ---------------------------------------------------------------- summation
-// Density sums: plain in FP64; in FP32 compensated (Knuth two-sum, Neumaier-style
-// running correction) so that the deviation density keeps full FP32 accuracy.
+// Density sums: plain in FP64; in FP32 the nine terms are added in FP64 and the sum is
+// rounded once, so that the deviation density keeps full FP32 accuracy.  An FP32 value
+// converts to FP64 exactly and the FP64 vector unit runs at the FP32 (unpacked) rate, so
+// this costs 10 conversions and 8 additions where a compensated FP32 two-sum costs 7
+// instructions per term; the partial sums are exact unless the terms span more than 29
+// binary orders of magnitude.
 template <typename T> struct Acc {
     T s;
     __device__ explicit Acc(T x) : s(x) {}
@@ -190,29 +196,29 @@ template <typename T> struct Acc {
     __device__ T sum() const { return s; }
 };
 template <> struct Acc<float> {
-    float s, c;
-    __device__ explicit Acc(float x) : s(x), c(0.0f) {}
-    __device__ void add(float x) {
-        float t = s + x;
-        float z = t - s;
-        c += (s - (t - z)) + (x - z);
-        s = t;
-    }
-    __device__ float sum() const { return s + c; }
+    double s;
+    __device__ explicit Acc(float x) : s((double)x) {}
+    __device__ void add(float x) { s += (double)x; }
+    __device__ float sum() const { return (float)s; }
 };
 
 // ---------------------------------------------------------------- equilibrium
 // Deviation of the D2Q9 equilibrium (Sec. 2.1, Eq. equilibrium) from the reference F_a, in
 // terms of u-hat = u / c (then xi.u / RT = 3 e.u-hat, (xi.u)^2/(2 RT^2) = 4.5 (e.u-hat)^2,
 // |u|^2/(2 RT) = 1.5 |u-hat|^2):  with U0 = 0, dfeq_a = w_a (drho + rho P_a).
+// fused multiply-add in the type itself, also in host code (where fma of floats would
+// round through double)
+__host__ __device__ __forceinline__ float fmaT(float a, float b, float c) { return fmaf(a, b, c); }
+__host__ __device__ __forceinline__ double fmaT(double a, double b, double c) { return fma(a, b, c); }
+
 template <typename T>
-__device__ __forceinline__ T usq_term(T ux, T uy) {
-    return (T)1.5 * fma(ux, ux, uy * uy);
+__host__ __device__ __forceinline__ T usq_term(T ux, T uy) {
+    return (T)1.5 * fmaT(ux, ux, uy * uy);
 }
 
 // e_a . v for the unit directions (exact: additions only)
 template <typename T>
-__device__ __forceinline__ T edot(int A, T vx, T vy) {
+__host__ __device__ __forceinline__ T edot(int A, T vx, T vy) {
     const T px = EX[A] > 0 ? vx : (EX[A] < 0 ? -vx : (T)0);
     const T py = EY[A] > 0 ? vy : (EY[A] < 0 ? -vy : (T)0);
     return EX[A] == 0 ? py : (EY[A] == 0 ? px : px + py);
@@ -223,11 +229,11 @@ __device__ __forceinline__ T edot(int A, T vx, T vy) {
 // make every collision add a little momentum.  FP32 therefore multiplies by the
 // weight as a two-term (hi + lo) constant; in FP64 the bias is below the parity bar.
 template <typename T>
-__device__ __forceinline__ T wmul(int A, T q) {
+__host__ __device__ __forceinline__ T wmul(int A, T q) {
     return (T)wgt(A) * q;
 }
 template <>
-__device__ __forceinline__ float wmul<float>(int A, float q) {
+__host__ __device__ __forceinline__ float wmul<float>(int A, float q) {
     const float hi = (float)wgt(A);
     const float lo = (float)(wgt(A) - (double)hi);
     return fmaf(hi, q, lo * q);
@@ -240,12 +246,13 @@ __device__ __forceinline__ float wmul<float>(int A, float q) {
 // Deviation storage holds x_a = f~_a - F_a with F_a = feq_a(rho0, U0): drho = rho - rho0
 // and (mx, my) = rho u/c - rho0 U0/c are deviations, and q0 = rho0 (4.5 (e_a.U0/c)^2 -
 // 1.5 |U0/c|^2) removes the reference's second-order part (0 when U0 = 0).
+// (Also evaluated on the host, with the same operations, for the inflow ghost values.)
 template <typename T>
-__device__ __forceinline__ T dfeq(int A, T drho, T rho, T mx, T my, T ux, T uy, T usq15, T q0 = (T)0) {
+__host__ __device__ __forceinline__ T dfeq(int A, T drho, T rho, T mx, T my, T ux, T uy, T usq15, T q0 = (T)0) {
     const T eu = edot<T>(A, ux, uy);
     const T em = edot<T>(A, mx, my);
-    const T q2 = fma((T)4.5 * eu, eu, -usq15);
-    return wmul<T>(A, fma(rho, q2, fma((T)3, em, drho) - q0));
+    const T q2 = fmaT((T)4.5 * eu, eu, -usq15);
+    return wmul<T>(A, fmaT(rho, q2, fmaT((T)3, em, drho) - q0));
 }
 
 // 1 / rho.  FP64: the hardware reciprocal refined by two Newton steps y += y (1 - r y)
@@ -348,6 +355,7 @@ struct March {
     uint32_t lbyte, sbyte;     // byte offset, within its row, of the slot this lane loads / stores
     bool per_x, per_y;
     bool ghostW, ghostE;       // this wave holds the west / east ghost column
+    bool wallW, symW, wallE, symE;   // ... and that side is a wall / symmetry side
     bool segS, segN;           // this lane's column lies in the south / north wall segment
     int laneE;                 // lane of column nx
     // per-lane face/cell coefficients
@@ -356,7 +364,7 @@ struct March {
     T dxs;                     // hc / (xc_{i+1} - xc_{i-1})
     T cdx;                     // dt c / dx_i
 
-    __device__ March(const StepParams<T> &p, const S *s, S *d, int x0) : P(p), src(s), dst(d) {
+    __device__ __forceinline__ March(const StepParams<T> &p, const S *s, S *d, int x0) : P(p), src(s), dst(d) {
         lane = threadIdx.x & 63;
         col = x0 - HALO + lane;
         const int nx = P.nx;
@@ -376,6 +384,10 @@ struct March {
         segN = BND && P.wfrom[SIDE_N] >= 0 && col >= P.wfrom[SIDE_N];
         laneE = nx - x0 + HALO;
         ghostE = BND && !per_x && laneE <= 63;
+        wallW = ghostW && P.bc[SIDE_W] == BC_WALL;
+        symW = ghostW && P.bc[SIDE_W] == BC_SYMMETRY;
+        wallE = ghostE && P.bc[SIDE_E] == BC_WALL;
+        symE = ghostE && P.bc[SIDE_E] == BC_SYMMETRY;
         const T *lam = P.xm, *id = P.xm + (nx + 1), *is = P.xm + 2 * (nx + 1), *cd = is + nx;
         // HALO = 1: a halo lane only needs the face it shares with the strip; HALO = 2 on a
         // periodic x axis: every lane advances its own (wrapped) column once, so it takes
@@ -451,36 +463,49 @@ struct March {
 
     // ---- ghost cells (Sec. 2.5, readings R5 / R6 / R17): one ghost value per direction
     // from the two nearest interior values g1 (adjacent) and g2 (next) of that direction,
-    // or gm, the adjacent value of the mirrored direction (symmetry side).
-    __device__ __forceinline__ T ghost_rule(int A, int side, T g1, T g2, T gm) const {
+    // or gm, the adjacent value of the mirrored direction (symmetry side).  Wall and
+    // first-order outflow: linear extrapolation g1 + gext (g1 - g2) with gext = ext;
+    // zero-order outflow: g1 (gext = 0); inflow: the equilibrium of the inflow state,
+    // formed on the host (gin).  A side's constants are loaded once per row, before its nine
+    // directions, and every choice is a select: no branch and no load inside the loop.
+    struct GhostRule {
+        bool sym, inflow;
+        T e, c[9];
+    };
+    __device__ __forceinline__ GhostRule ghost_rule(int side) const {
+        GhostRule r;
         const int k = P.bc[side];
-        if (k == BC_SYMMETRY) return gm;
-        if (k == BC_INFLOW) {
-            const T rho = P.bcv[side][0], ux = P.bcv[side][1], uy = P.bcv[side][2];
-            const T mx = kRefVel<T> ? fma(rho, ux, -P.m0x) : rho * ux;
-            const T my = kRefVel<T> ? fma(rho, uy, -P.m0y) : rho * uy;
-            return dfeq(A, rho - P.rho0, rho, mx, my, ux, uy, usq_term(ux, uy), kRefVel<T> ? P.q0[A] : (T)0);
-        }
-        if (k == BC_OUTFLOW && P.bcv[side][0] < (T)0.5) return g1;
-        return fma(g1 - g2, P.ext[side], g1);   // wall and first-order outflow
+        r.sym = k == BC_SYMMETRY;
+        r.inflow = k == BC_INFLOW;
+        r.e = P.gext[side];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) r.c[a] = P.gin[side][a];
+        return r;
+    }
+    __device__ __forceinline__ static T ghost_value(const GhostRule &r, int A, T g1, T g2, T gm) {
+        T g = fma(g1 - g2, r.e, g1);
+        g = r.inflow ? r.c[A] : g;
+        return r.sym ? gm : g;
     }
     // x-side ghost lanes of one row (x-sides first, as in Sec. 2.5 reading R5)
     __device__ __forceinline__ void ghost_x(T (&phi)[9]) const {
         // only the ghost lane is written, and it reads its interior neighbours, so the
         // directions may be filled in place in any order
         if (ghostW) {
+            const GhostRule r = ghost_rule(SIDE_W);
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
                 T g1 = shl1(phi[a]), g2 = shl1(g1);
-                T g = ghost_rule(a, SIDE_W, g1, g2, shl1(phi[MIRX[a]]));
+                T g = ghost_value(r, a, g1, g2, shl1(phi[MIRX[a]]));
                 phi[a] = lane == HALO - 1 ? g : phi[a];
             }
         }
         if (ghostE) {
+            const GhostRule r = ghost_rule(SIDE_E);
 #pragma unroll
             for (int a = 0; a < 9; ++a) {
                 T g1 = shr1(phi[a]), g2 = shr1(g1);
-                T g = ghost_rule(a, SIDE_E, g1, g2, shr1(phi[MIRX[a]]));
+                T g = ghost_value(r, a, g1, g2, shr1(phi[MIRX[a]]));
                 phi[a] = lane == laneE ? g : phi[a];
             }
         }
@@ -489,10 +514,12 @@ struct March {
     // Lanes in the side's wall segment take the wall rule.
     __device__ __forceinline__ void ghost_y(int side, const T (&r1)[9], const T (&r2)[9], T (&out)[9]) const {
         const bool seg = side == SIDE_S ? segS : segN;
+        const GhostRule r = ghost_rule(side);
+        const T ext = P.ext[side];
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
-            const T g = ghost_rule(a, side, r1[a], r2[a], r1[MIRY[a]]);
-            out[a] = seg ? fma(r1[a] - r2[a], P.ext[side], r1[a]) : g;
+            const T g = ghost_value(r, a, r1[a], r2[a], r1[MIRY[a]]);
+            out[a] = seg ? fma(r1[a] - r2[a], ext, r1[a]) : g;
         }
     }
 
@@ -592,12 +619,10 @@ struct March {
         }
         T fW[9];
         xface(P0, dy, isy, fW);
-        if (ghostW && P.bc[SIDE_W] == BC_WALL)
-            bounce<-1, 0>(fW, P.bcv[SIDE_W][0], P.bcv[SIDE_W][1], lane == HALO);
-        if (ghostW && P.bc[SIDE_W] == BC_SYMMETRY) specular<-1, 0>(fW, lane == HALO);
-        if (ghostE && P.bc[SIDE_E] == BC_WALL)
-            bounce<1, 0>(fW, P.bcv[SIDE_E][0], P.bcv[SIDE_E][1], lane == laneE);
-        if (ghostE && P.bc[SIDE_E] == BC_SYMMETRY) specular<1, 0>(fW, lane == laneE);
+        if (wallW) bounce<-1, 0>(fW, P.bcv[SIDE_W][0], P.bcv[SIDE_W][1], lane == HALO);
+        if (symW) specular<-1, 0>(fW, lane == HALO);
+        if (wallE) bounce<1, 0>(fW, P.bcv[SIDE_E][0], P.bcv[SIDE_E][1], lane == laneE);
+        if (symE) specular<1, 0>(fW, lane == laneE);
         face_mix<0>(fW);
 
         // y-face north of row r
@@ -700,6 +725,7 @@ struct March {
         T v[9];
         advance(r, Pm, P0, Pp, S0, fS, v);     // level 1 of row k
         cell_t(v, Qk, Uk);
+        ghost_x(Qk);
         if (PHASE < 0 ? k == j0 : PHASE == 1) {
             yface(j0, Qm1, Qk, gS);           // level-1 face south of row j0
             face_mix<1>(gS);
@@ -708,7 +734,10 @@ struct March {
             advance(k - 1, Qm2, Qm1, Qk, Um1, gS, w);   // level 2 of row k-1
             store_row(k - 1, w);
         }
-        if (need_next) cell(R, Pm, Sm);
+        if (need_next) {
+            cell(R, Pm, Sm);
+            ghost_x(Pm);
+        }
     }
 
     __device__ __forceinline__ void run(int j0, int j1) {
@@ -758,7 +787,9 @@ struct March {
         }
     }
 
-    // two steps per pass over rows [j0, j1) of a periodic mesh (HALO = 2)
+    // two steps per pass over rows [j0, j1) (HALO = 2) of a periodic mesh, or of a row block
+    // clear of non-periodic y sides (rows j0-2 .. j1+1 in the mesh); the x-side ghost lanes
+    // are refilled after every cell stage of both levels, as in run2b
     __device__ __forceinline__ void run2(int j0, int j1) {
         T PA[9], PB[9], PC[9], SA[9], SB[9], SC[9], fS[9];
         T QA[9], QB[9], QC[9], UA[9], UB[9], UC[9], gS[9];
@@ -768,8 +799,11 @@ struct March {
         load(j0 - 1, R1);
         load(j0, R2);
         cell(R, PA, SA);
+        ghost_x(PA);
         cell(R1, PB, SB);
+        ghost_x(PB);
         cell(R2, PC, SC);
+        ghost_x(PC);
         yface(row_index(j0 - 1), PA, PB, fS);
         face_mix<1>(fS);
 
@@ -832,7 +866,10 @@ struct March {
         T v[9];
         advance(r, Pm, P0, Pp, S0, fS, v);     // level 1 of row k
         ring_put(ring, t & 1, v);
-        if (need_next) cell(R, Pm, Sm);
+        if (need_next) {
+            cell(R, Pm, Sm);
+            ghost_x(Pm);
+        }
         __syncthreads();
     }
     __device__ __forceinline__ void produce(int j0, int j1, T *ring) {
@@ -842,8 +879,11 @@ struct March {
         load(j0 - 1, R1);
         load(j0, R2);
         cell(R, PA, SA);
+        ghost_x(PA);
         cell(R1, PB, SB);
+        ghost_x(PB);
         cell(R2, PC, SC);
+        ghost_x(PC);
         yface(row_index(j0 - 1), PA, PB, fS);
         face_mix<1>(fS);
         int t = 0;
@@ -864,6 +904,7 @@ struct March {
         T v[9];
         ring_get(ring, t & 1, v);
         cell_t(v, Qk, Uk);
+        ghost_x(Qk);
         if (k == j0) {
             yface(j0, Qm1, Qk, gS);           // level-1 face south of row j0
             face_mix<1>(gS);
@@ -1185,9 +1226,10 @@ __global__ __launch_bounds__(128) void step2p_kernel(StepParams<T> P, int parity
 }
 
 // Two time steps per launch on a mesh with a non-periodic side (60-column strip layout),
-// parameters by value (the FP64 forms on the DUGKS march). Waves whose columns
-// x0-2 .. x0+61 and rows j0-2 .. j1+1 all lie inside the mesh (or wrap on a periodic axis)
-// need no ghost cells: they take the periodic march, whose rows rotate without copies.
+// parameters by value (the FP64 forms on the DUGKS march). Waves whose rows j0-2 .. j1+1
+// all lie inside the mesh (or wrap on a periodic y axis) need no ghost rows: they take the
+// rotating march of run2, which refills the x-side ghost lanes where the strip has them;
+// only the row blocks at a non-periodic y side take run2b.
 template <typename T, typename S, int SCHEME>
 __global__ __launch_bounds__(256) void step2b_kernel(StepParams<T> P, int parity, int rows, int nstrips, int nwork) {
     const int rb = xcd_block();
@@ -1200,9 +1242,8 @@ __global__ __launch_bounds__(256) void step2b_kernel(StepParams<T> P, int parity
     S *dst = (S *)P.buf[parity ^ 1];
     const int x0 = P.strip * sx;
     March<T, S, SCHEME, true, 2> m(P, src, dst, x0);
-    const bool inner_x = m.per_x || (x0 >= 2 && x0 + 61 <= P.nx - 1);
     const bool inner_y = m.per_y || (j0 >= 2 && j1 <= P.ny - 2);
-    if (inner_x && inner_y) m.run2(j0, j1);
+    if (inner_y) m.run2(j0, j1);
     else m.run2b(j0, j1);
 }
 
@@ -1226,16 +1267,15 @@ __global__ __launch_bounds__(256) void step2b_ptr_kernel(const StepParams<T> *__
     S *dst = (S *)P.buf[parity ^ 1];
     const int x0 = P.strip * sx;
     March<T, S, SCHEME, true, 2> m(P, src, dst, x0);
-    const bool inner_x = m.per_x || (x0 >= 2 && x0 + 61 <= P.nx - 1);
     const bool inner_y = m.per_y || (j0 >= 2 && j1 <= P.ny - 2);
-    if (inner_x && inner_y) m.run2(j0, j1);
+    if (inner_y) m.run2(j0, j1);
     else m.run2b(j0, j1);
 }
 
 // Two time steps per launch on a mesh with a non-periodic side, split over a pair of waves
-// (one workgroup of two waves per work item; parameters through a device pointer): waves
-// clear of every side take produce / consume, the others produce_b / consume_b.  The same
-// bits as step2b_kernel.
+// (one workgroup of two waves per work item; parameters through a device pointer): row
+// blocks clear of the non-periodic y sides take produce / consume (with the x-side ghost
+// lanes refilled), the others produce_b / consume_b.  The same bits as step2b_kernel.
 template <typename T, typename S, int SCHEME>
 __global__ __launch_bounds__(128) void step2bp_kernel(const StepParams<T> *__restrict__ Pp, int parity, int rows,
                                                       int nstrips, int nwork) {
@@ -1249,10 +1289,9 @@ __global__ __launch_bounds__(128) void step2bp_kernel(const StepParams<T> *__res
     S *dst = (S *)P.buf[parity ^ 1];
     const int x0 = P.strip * sx;
     March<T, S, SCHEME, true, 2> m(P, src, dst, x0);
-    const bool inner_x = m.per_x || (x0 >= 2 && x0 + 61 <= P.nx - 1);
     const bool inner_y = m.per_y || (j0 >= 2 && j1 <= P.ny - 2);
     const bool producer = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) == 0;
-    if (inner_x && inner_y) {
+    if (inner_y) {
         if (producer) m.produce(j0, j1, ring);
         else m.consume(j0, j1, ring);
     } else {

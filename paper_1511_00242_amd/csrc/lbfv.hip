@@ -222,6 +222,18 @@ StepParams<T> make_params(const HostCase &h, double ext[4], int scheme = SCHEME_
             P.q0[a] = (T)(h.rho0 * (4.5 * eu * eu - 1.5 * (ux * ux + uy * uy)));
         }
     }
+    for (int s = 0; s < 4; ++s) {
+        P.gext[s] = (h.bc[s] == BC_OUTFLOW && h.bcval[s][0] < 0.5) ? (T)0 : P.ext[s];
+        if (h.bc[s] == BC_INFLOW) {
+            // the inflow ghost state, with the operations the kernels used to apply per cell
+            const T rho = P.bcv[s][0], ux = P.bcv[s][1], uy = P.bcv[s][2];
+            const T mx = kRefVel<T> ? fmaT(rho, ux, -P.m0x) : rho * ux;
+            const T my = kRefVel<T> ? fmaT(rho, uy, -P.m0y) : rho * uy;
+            for (int a = 0; a < 9; ++a)
+                P.gin[s][a] = dfeq<T>(a, rho - P.rho0, rho, mx, my, ux, uy, usq_term<T>(ux, uy),
+                                      kRefVel<T> ? P.q0[a] : (T)0);
+        }
+    }
     P.hc = (T)(hh * h.c);
     P.cb = (T)(3.0 * hh / (2.0 * tau + dt));
     P.cd = (T)(2.0 * dt / (2.0 * tau + dt));
