@@ -459,6 +459,21 @@ struct March {
                 phi[a] = fma(P.cd, d, x[a]);
             }
         }
+        if (sizeof(T) == 4 && sizeof(S) == 4) {
+            // The relaxation conserves the cell's mass in exact arithmetic, but the FP32
+            // roundings of the equilibrium's second-order terms and of the nine relaxed values
+            // do not sum to zero, and in a slowly varying flow a cell repeats the same
+            // roundings step after step: the total mass drifts steadily.  The rest direction
+            // (no flux) takes the remainder: its value is the exact density sum less the eight
+            // others, in FP64 (exact for FP32 terms) and rounded once.
+            T (&out)[9] = SCHEME == SCHEME_DUGKS ? psi : phi;
+            double r = (double)x[0];
+#pragma unroll
+            for (int a = 1; a < 9; ++a) r += (double)x[a];
+#pragma unroll
+            for (int a = 1; a < 9; ++a) r -= (double)out[a];
+            out[0] = (T)r;
+        }
     }
 
     // ---- ghost cells (Sec. 2.5, readings R5 / R6 / R17): one ghost value per direction
