@@ -1183,10 +1183,9 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams<T> P, int parity, 
 }
 
 // The one-step kernel of a mesh with a non-periodic side, parameters read through a device
-// pointer (all but the FP64 forms on the DUGKS march): by value they are held in scalar
-// registers and spill, and the boundary code then costs a wave per SIMD (FP64 BKG: 255 + 16
-// registers and one wave by value, 194 and two through the pointer; FP32 DUGKS 181 -> 142,
-// three waves instead of two).
+// pointer: by value they are held in scalar registers and spill, and the boundary code then
+// costs a wave per SIMD (FP64 BKG: 255 + 16 registers and one wave by value, 194 and two
+// through the pointer; FP32 DUGKS 181 -> 142, three waves instead of two).
 template <typename T, typename S, int SCHEME>
 __global__ __launch_bounds__(256) void step_ptr_kernel(const StepParams<T> *__restrict__ Pp, int parity, int rows,
                                                        int nstrips, int nwork) {
@@ -1241,33 +1240,12 @@ __global__ __launch_bounds__(128) void step2p_kernel(StepParams<T> P, int parity
 }
 
 // Two time steps per launch on a mesh with a non-periodic side (60-column strip layout),
-// parameters by value (the FP64 forms on the DUGKS march). Waves whose rows j0-2 .. j1+1
-// all lie inside the mesh (or wrap on a periodic y axis) need no ghost rows: they take the
-// rotating march of run2, which refills the x-side ghost lanes where the strip has them;
-// only the row blocks at a non-periodic y side take run2b.
-template <typename T, typename S, int SCHEME>
-__global__ __launch_bounds__(256) void step2b_kernel(StepParams<T> P, int parity, int rows, int nstrips, int nwork) {
-    const int rb = xcd_block();
-    const int wpb = blockDim.x >> 6;
-    const int w = __builtin_amdgcn_readfirstlane(rb * wpb + (int)(threadIdx.x >> 6));
-    if (w >= nwork) return;
-    const int sx = w % nstrips, sy = w / nstrips;
-    const int j0 = sy * rows, j1 = min(P.ny, j0 + rows);
-    const S *src = (const S *)P.buf[parity];
-    S *dst = (S *)P.buf[parity ^ 1];
-    const int x0 = P.strip * sx;
-    March<T, S, SCHEME, true, 2> m(P, src, dst, x0);
-    const bool inner_y = m.per_y || (j0 >= 2 && j1 <= P.ny - 2);
-    if (inner_y) m.run2(j0, j1);
-    else m.run2b(j0, j1);
-}
-
-// The same with the parameters read through a device pointer (BKG, and the FP32 forms). By
-// value they are held in scalar registers across both inlined marches and spill; through a
-// pointer the FP64 BKG form needs no scratch and fits two waves per SIMD instead of one. The
-// FP64 DUGKS form measured faster by value. The body is repeated rather than shared through a device function: the
-// compiler allocates the two differently when called through one (more scratch by value,
-// scalar spills through the pointer).
+// parameters read through a device pointer: by value they are held in scalar registers
+// across both inlined marches and spill (FP64 DUGKS: 744 bytes of scratch per lane and
+// 0.59 ms per step on the 4096^2 cavity, against none and 0.47 ms through the pointer).
+// Waves whose rows j0-2 .. j1+1 all lie inside the mesh (or wrap on a periodic y axis) need
+// no ghost rows: they take the rotating march of run2, which refills the x-side ghost lanes
+// where the strip has them; only the row blocks at a non-periodic y side take run2b.
 template <typename T, typename S, int SCHEME>
 __global__ __launch_bounds__(256) void step2b_ptr_kernel(const StepParams<T> *__restrict__ Pp, int parity, int rows,
                                                          int nstrips, int nwork) {
@@ -1290,7 +1268,7 @@ __global__ __launch_bounds__(256) void step2b_ptr_kernel(const StepParams<T> *__
 // Two time steps per launch on a mesh with a non-periodic side, split over a pair of waves
 // (one workgroup of two waves per work item; parameters through a device pointer): row
 // blocks clear of the non-periodic y sides take produce / consume (with the x-side ghost
-// lanes refilled), the others produce_b / consume_b.  The same bits as step2b_kernel.
+// lanes refilled), the others produce_b / consume_b.  The same bits as step2b_ptr_kernel.
 template <typename T, typename S, int SCHEME>
 __global__ __launch_bounds__(128) void step2bp_kernel(const StepParams<T> *__restrict__ Pp, int parity, int rows,
                                                       int nstrips, int nwork) {

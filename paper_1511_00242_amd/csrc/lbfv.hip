@@ -310,20 +310,17 @@ StepShape step_shape(const HostCase &h, int rows, int wpb) {
     return s;
 }
 
-// Kernels of a mesh with a non-periodic side read their parameters through a device copy,
-// except the FP64 forms built on the DUGKS march (DUGKS, central, upwind), which measured
-// faster with them by value; doubly periodic meshes pass them by value.
-bool params_by_pointer(int variant, int scheme, bool bnd) {
-    return bnd && (variant != V_F64 || scheme == SCHEME_BKG);
-}
+// Kernels of a mesh with a non-periodic side read their parameters through a device copy
+// (passed by value, the parameters of the longer march with sides spill from the scalar
+// registers); doubly periodic meshes pass them by value.
+bool params_by_pointer(int, int, bool bnd) { return bnd; }
 
 // one step per launch
 template <typename T, typename S>
 void *step_fn(int scheme, bool bnd) {
     if (bnd) {
-        if (scheme == SCHEME_BKG) return (void *)step_ptr_kernel<T, S, SCHEME_BKG>;
-        if constexpr (std::is_same<T, double>::value) return (void *)step_kernel<T, S, SCHEME_DUGKS, true>;
-        else return (void *)step_ptr_kernel<T, S, SCHEME_DUGKS>;
+        return scheme == SCHEME_BKG ? (void *)step_ptr_kernel<T, S, SCHEME_BKG>
+                                    : (void *)step_ptr_kernel<T, S, SCHEME_DUGKS>;
     }
     return scheme == SCHEME_BKG ? (void *)step_kernel<T, S, SCHEME_BKG, false>
                                 : (void *)step_kernel<T, S, SCHEME_DUGKS, false>;
@@ -331,9 +328,8 @@ void *step_fn(int scheme, bool bnd) {
 template <typename T, typename S>
 void *step2_fn(int scheme, bool bnd) {
     if (bnd) {
-        if (scheme == SCHEME_BKG) return (void *)step2b_ptr_kernel<T, S, SCHEME_BKG>;
-        if constexpr (std::is_same<T, double>::value) return (void *)step2b_kernel<T, S, SCHEME_DUGKS>;
-        else return (void *)step2b_ptr_kernel<T, S, SCHEME_DUGKS>;
+        return scheme == SCHEME_BKG ? (void *)step2b_ptr_kernel<T, S, SCHEME_BKG>
+                                    : (void *)step2b_ptr_kernel<T, S, SCHEME_DUGKS>;
     }
     return scheme == SCHEME_BKG ? (void *)step2_kernel<T, S, SCHEME_BKG> : (void *)step2_kernel<T, S, SCHEME_DUGKS>;
 }
