@@ -329,12 +329,15 @@ __device__ __forceinline__ void dfeq_pair_unweighted(int A, const Mom<T> &m, T q
     Qr = A == 0 ? s : fma((T)-3, em, s);
 }
 // dfeq - x from the unweighted deviation Q.  FP64 folds the weight into one fused
-// multiply-add (one rounding, one instruction fewer per direction); FP32 keeps the
-// two-term weight product.
+// multiply-add (one rounding).  FP32 keeps the two-term weight: hi Q - x first, in one
+// fused operation (near equilibrium the cancellation happens there, with the product
+// exact), then the small lo Q added by a second one; two instructions.
 template <typename T>
 __device__ __forceinline__ T wsub(int A, T Q, T x) {
     if (sizeof(T) == 8) return fma((T)wgt(A), Q, -x);
-    return wmul<T>(A, Q) - x;
+    const float hi = (float)wgt(A);
+    const float lo = (float)(wgt(A) - (double)hi);
+    return fmaf(lo, Q, fmaf(hi, Q, -x));
 }
 // The representative of each direction pair (A, REV[A]): 0 (alone), 1, 2, 5, 6.
 __device__ __forceinline__ constexpr int pair_rep(int k) { return k == 0 ? 0 : (k == 1 ? 1 : (k == 2 ? 2 : (k == 3 ? 5 : 6))); }
