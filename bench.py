@@ -31,7 +31,6 @@ HEADLINE_TIME_BLOCK = 2        # steps per launch (fixed so that the committed c
                                # describes the same launches)
 HEADLINE_PAIRS = 1             # two steps per launch: one wave (0) or a pair of waves (1) per item
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_dugks_fp64_taylor_green_4096.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1511_00242_amd", "csrc", "kernels.hpp")
 BYTES = {"f64": 144, "f32": 72, "bf16": 36, "f16": 36}   # algorithmic bytes per cell-step (9 reads + 9 writes)
 
 
@@ -394,21 +393,22 @@ def boundary_layer_paper(a, stream):
     return out
 
 
-def kernel_code_hash(path=KERNEL_SOURCE):
-    """sha256 of the kernel source with comments and whitespace removed: a profile stays
-    valid across edits of comments only."""
-    import hashlib
-    import re
-    text = open(path).read()
-    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
-    text = re.sub(r"//[^\n]*", " ", text)
-    return hashlib.sha256(" ".join(text.split()).encode()).hexdigest()
+HEADLINE_KERNEL = "_ZN4lbfv13step2p_kernelIddLi0EEEvNS_10StepParamsIT_EEiiii"   # step2p_kernel<double,double,DUGKS>
+
+
+def kernel_isa_hash():
+    """sha256 of the headline kernel's machine code and kernel descriptor in the loaded
+    library: a counter profile stays valid exactly as long as the binary kernel it measured."""
+    from paper_1511_00242_amd import codeobj
+    from paper_1511_00242_amd import lbfv as L
+    return codeobj.kernel_isa_sha256(L._LIB_PATH, HEADLINE_KERNEL)
 
 
 def profiled_traffic(tile, time_block, ms_per_step, pairs=0):
     """HBM traffic of the headline kernel from the committed rocprofv3 counter summary:
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the same counters read for a
-    plain 1 GiB device copy.  None when the kernel source or the launch shape changed since."""
+    plain 1 GiB device copy.  None when the kernel's machine code or the launch shape changed
+    since."""
     if not os.path.exists(TRAFFIC_PROFILE):
         return None, None
     kv = {}
@@ -417,7 +417,8 @@ def profiled_traffic(tile, time_block, ms_per_step, pairs=0):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     try:
-        if (kv.get("kernel_code_sha256") != kernel_code_hash() or kv.get("tile") != f"{tile[0]},{tile[1]}"
+        isa = kernel_isa_hash()
+        if (isa is None or kv.get("kernel_isa_sha256") != isa or kv.get("tile") != f"{tile[0]},{tile[1]}"
                 or kv.get("time_block", "1") != str(time_block) or kv.get("wave_pairs", "0") != str(pairs)):
             return None, None
         b = (float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])

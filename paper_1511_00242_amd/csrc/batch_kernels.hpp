@@ -28,7 +28,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const StepParams<T> *__restr
         const StepParams<T> &P = cases[it.c];
         const S *src = (const S *)P.buf[parity];
         S *dst = (S *)P.buf[parity ^ 1];
-        March<T, S, SCHEME, BND> m(P, src, dst, it.x0);
+        March<T, S, SCHEME, BND, 1, false> m(P, src, dst, it.x0);
         m.run(it.j0, it.j1);
     }
 }
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) void batch2_kernel(const StepParams<T> *__rest
         const StepParams<T> &P = cases[it.c];
         const S *src = (const S *)P.buf[parity];
         S *dst = (S *)P.buf[parity ^ 1];
-        March<T, S, SCHEME, BND, 2> m(P, src, dst, it.x0);
+        March<T, S, SCHEME, BND, 2, false> m(P, src, dst, it.x0);
         if constexpr (BND) {
             const bool inner_y = m.per_y || (it.j0 >= 2 && it.j1 <= P.ny - 2);
             if (inner_y) m.run2(it.j0, it.j1);
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(128) void batch2p_kernel(const StepParams<T> *__res
         const StepParams<T> &P = cases[it.c];
         const S *src = (const S *)P.buf[parity];
         S *dst = (S *)P.buf[parity ^ 1];
-        March<T, S, SCHEME, BND, 2> m(P, src, dst, it.x0);
+        March<T, S, SCHEME, BND, 2, false> m(P, src, dst, it.x0);
         bool inner = true;
         if constexpr (BND) inner = m.per_y || (it.j0 >= 2 && it.j1 <= P.ny - 2);
         if (inner) {

@@ -275,20 +275,21 @@ __device__ __forceinline__ double recip<double>(double r) {
 template <>
 __device__ __forceinline__ float recip<float>(float r) { return __builtin_amdgcn_rcpf(r); }
 
-// The reference-velocity terms are compiled for FP32 compute only (FP64 compute stores
-// f~ itself, so its reference state is zero).
+// The reference-velocity terms (REF below) are compiled for FP32 compute only (FP64 compute
+// stores f~ itself, so its reference state is zero), and not for the batch, whose cases store
+// deviations from w_a rho0 with no reference velocity.
 template <typename T>
 constexpr bool kRefVel = sizeof(T) == 4;
 
 // Moments of a 9-vector of deviations: drho = sum x, m = sum e x (the momentum less the
 // reference momentum m0 = rho0 U0 / c), the momentum M = m + m0 = rho u-hat and 1 / rho.
 // COMP: compensated density sum (cell moments; the face moments enter only through the
-// small back-transform weight h / (2 tau + h) and use a plain sum).
+// small back-transform weight h / (2 tau + h) and use a plain sum).  REF = false: m0 = 0.
 template <typename T>
 struct Mom {
     T drho, rho, inv, mx, my, Mx, My, msq15;
 };
-template <typename T, bool COMP = true>
+template <typename T, bool COMP = true, bool REF = kRefVel<T>>
 __device__ __forceinline__ Mom<T> moments(const T (&x)[9], T rho0, T m0x, T m0y) {
     Mom<T> m;
     if (COMP) {
@@ -304,7 +305,7 @@ __device__ __forceinline__ Mom<T> moments(const T (&x)[9], T rho0, T m0x, T m0y)
     const T d57 = x[5] - x[7], d86 = x[8] - x[6];   // shared by both components
     m.mx = ((x[1] - x[3]) + d57) + d86;
     m.my = ((x[2] - x[4]) + d57) - d86;
-    if (kRefVel<T>) {
+    if (REF) {
         m.Mx = m.mx + m0x;
         m.My = m.my + m0y;
     } else {
@@ -321,12 +322,12 @@ __device__ __forceinline__ Mom<T> moments(const T (&x)[9], T rho0, T m0x, T m0y)
 // the sign of e), so both are s +- 3 e.m with s = drho + q / rho formed once (4
 // instructions saved per pair, a tenth of the step's arithmetic with the two face mixes
 // counted).  A = 0 (no reverse): s.
-template <typename T>
+template <typename T, bool REF = kRefVel<T>>
 __device__ __forceinline__ void dfeq_pair_unweighted(int A, const Mom<T> &m, T q0, T &Qa, T &Qr) {
     const T eM = edot<T>(A, m.Mx, m.My);
-    const T em = kRefVel<T> ? edot<T>(A, m.mx, m.my) : eM;
+    const T em = REF ? edot<T>(A, m.mx, m.my) : eM;
     const T q = A == 0 ? -m.msq15 : fma((T)4.5 * eM, eM, -m.msq15);
-    const T s = fma(m.inv, q, kRefVel<T> ? m.drho - q0 : m.drho);
+    const T s = fma(m.inv, q, REF ? m.drho - q0 : m.drho);
     Qa = A == 0 ? s : fma((T)3, em, s);
     Qr = A == 0 ? s : fma((T)-3, em, s);
 }
@@ -350,7 +351,8 @@ __device__ __forceinline__ constexpr int pair_rep(int k) { return k == 0 ? 0 : (
 // the register budget of the interior loop small.  HALO = 1: one step per pass, lane l
 // holds column x0-1+l; HALO = 2: two steps per pass, lane l holds column x0-2+l and the
 // intermediate step stays in registers (run2 on doubly periodic meshes, run2b with sides).
-template <typename T, typename S, int SCHEME, bool BND, int HALO = 1>
+// REF = false compiles out the reference-velocity terms (m0 = q0 = 0).
+template <typename T, typename S, int SCHEME, bool BND, int HALO = 1, bool REF = kRefVel<T>>
 struct March {
     const StepParams<T> &P;
     const S *__restrict__ src;
@@ -447,12 +449,12 @@ struct March {
         cell_t(x, phi, psi);
     }
     __device__ __forceinline__ void cell_t(const T (&x)[9], T (&phi)[9], T (&psi)[9]) const {
-        const Mom<T> m = moments(x, P.rho0, P.m0x, P.m0y);
+        const Mom<T> m = moments<T, true, REF>(x, P.rho0, P.m0x, P.m0y);
         T Q[9];
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
             const int A = pair_rep(k);
-            dfeq_pair_unweighted(A, m, P.q0[A], Q[A], Q[REV[A]]);
+            dfeq_pair_unweighted<T, REF>(A, m, P.q0[A], Q[A], Q[REV[A]]);
         }
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
@@ -575,14 +577,14 @@ struct March {
     template <int AX>
     __device__ __forceinline__ void face_mix(T (&fb)[9]) const {
         if (SCHEME == SCHEME_DUGKS) {
-            const Mom<T> m = moments<T, false>(fb, P.rho0, P.m0x, P.m0y);
+            const Mom<T> m = moments<T, false, REF>(fb, P.rho0, P.m0x, P.m0y);
             // the directions crossing the face come in reverse pairs: (1, 3) or (2, 4), (5, 7), (6, 8)
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const int A = k == 0 ? (AX == 0 ? 1 : 2) : (k == 1 ? 5 : 6);
                 const int R = REV[A];
                 T Qa, Qr;
-                dfeq_pair_unweighted(A, m, P.q0[A], Qa, Qr);
+                dfeq_pair_unweighted<T, REF>(A, m, P.q0[A], Qa, Qr);
                 fb[A] = fma(P.m2, wsub(A, Qa, fb[A]), fb[A]);
                 fb[R] = fma(P.m2, wsub(R, Qr, fb[R]), fb[R]);
             }

@@ -63,3 +63,18 @@ def test_pair_kernels_fit_two_waves_per_simd(tmp_path):
     for k, v in md.items():
         if "step2p_kernelIdd" in k or "step2bp_kernelIdd" in k:
             assert v["vgpr_count"] <= 256, (k, v)
+
+
+def test_kernel_digest_identifies_the_binary_kernel():
+    # the digest bench.py ties a counter profile to: stable, and distinct per kernel
+    from paper_1511_00242_amd import codeobj
+    lib = L._LIB_PATH
+    if not os.path.exists(lib):
+        pytest.skip("liblbfv.so is not built")
+    head = "_ZN4lbfv13step2p_kernelIddLi0EEEvNS_10StepParamsIT_EEiiii"
+    bkg = "_ZN4lbfv13step2p_kernelIddLi1EEEvNS_10StepParamsIT_EEiiii"
+    h1, h2, h3 = (codeobj.kernel_isa_sha256(lib, k) for k in (head, head, bkg))
+    if h1 is None:
+        pytest.skip("ROCm LLVM tools not found")
+    assert re.fullmatch(r"[0-9a-f]{64}", h1) and h1 == h2 and h1 != h3
+    assert codeobj.kernel_isa_sha256(lib, "no_such_kernel") is None
