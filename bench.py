@@ -393,7 +393,7 @@ def boundary_layer_paper(a, stream):
     return out
 
 
-HEADLINE_KERNEL = "_ZN4lbfv13step2p_kernelIddLi0EEEvNS_10StepParamsIT_EEiiii"   # step2p_kernel<double,double,DUGKS>
+HEADLINE_KERNEL = "_ZN4lbfv13step2p_kernelIddLi0ELb0EEEvNS_10StepParamsIT_EEiiii"   # step2p_kernel<double,double,DUGKS>
 
 
 def kernel_isa_hash():

@@ -276,8 +276,9 @@ template <>
 __device__ __forceinline__ float recip<float>(float r) { return __builtin_amdgcn_rcpf(r); }
 
 // The reference-velocity terms (REF below) are compiled for FP32 compute only (FP64 compute
-// stores f~ itself, so its reference state is zero), and not for the batch, whose cases store
-// deviations from w_a rho0 with no reference velocity.
+// stores f~ itself, so its reference state is zero).  The step kernels take REF as a template
+// argument, and the host picks the form without them unless a reference velocity is set; the
+// batch, whose cases store deviations from w_a rho0, never uses them.
 template <typename T>
 constexpr bool kRefVel = sizeof(T) == 4;
 
@@ -1174,7 +1175,7 @@ __device__ __forceinline__ int xcd_block() {
 
 // One launch = one time step of one case.  Work item w -> (strip, row block); each wave
 // takes one item, and consecutive items (neighbouring strips, then row blocks) share an XCD.
-template <typename T, typename S, int SCHEME, bool BND>
+template <typename T, typename S, int SCHEME, bool BND, bool REF>
 __global__ __launch_bounds__(256) void step_kernel(StepParams<T> P, int parity, int rows, int nstrips,
                                                    int nwork) {
     const int rb = xcd_block();
@@ -1185,7 +1186,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams<T> P, int parity, 
     const int j0 = sy * rows, j1 = min(P.ny, j0 + rows);
     const S *src = (const S *)P.buf[parity];
     S *dst = (S *)P.buf[parity ^ 1];
-    March<T, S, SCHEME, BND> m(P, src, dst, P.strip * sx);
+    March<T, S, SCHEME, BND, 1, REF> m(P, src, dst, P.strip * sx);
     m.run(j0, j1);
 }
 
@@ -1193,7 +1194,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepParams<T> P, int parity, 
 // pointer: by value they are held in scalar registers and spill, and the boundary code then
 // costs a wave per SIMD (FP64 BKG: 255 + 16 registers and one wave by value, 194 and two
 // through the pointer; FP32 DUGKS 181 -> 142, three waves instead of two).
-template <typename T, typename S, int SCHEME>
+template <typename T, typename S, int SCHEME, bool REF>
 __global__ __launch_bounds__(256) void step_ptr_kernel(const StepParams<T> *__restrict__ Pp, int parity, int rows,
                                                        int nstrips, int nwork) {
     const StepParams<T> &P = *Pp;
@@ -1205,14 +1206,14 @@ __global__ __launch_bounds__(256) void step_ptr_kernel(const StepParams<T> *__re
     const int j0 = sy * rows, j1 = min(P.ny, j0 + rows);
     const S *src = (const S *)P.buf[parity];
     S *dst = (S *)P.buf[parity ^ 1];
-    March<T, S, SCHEME, true> m(P, src, dst, P.strip * sx);
+    March<T, S, SCHEME, true, 1, REF> m(P, src, dst, P.strip * sx);
     m.run(j0, j1);
 }
 
 // Two time steps per launch on a doubly periodic mesh (state in the 60-column strip
 // layout): each wave reads its strip once, keeps the intermediate step in registers and
 // stores the second; a launch reads buf[parity] and writes buf[1-parity].
-template <typename T, typename S, int SCHEME>
+template <typename T, typename S, int SCHEME, bool REF>
 __global__ __launch_bounds__(256) void step2_kernel(StepParams<T> P, int parity, int rows, int nstrips,
                                                     int nwork) {
     const int rb = xcd_block();
@@ -1223,7 +1224,7 @@ __global__ __launch_bounds__(256) void step2_kernel(StepParams<T> P, int parity,
     const int j0 = sy * rows, j1 = min(P.ny, j0 + rows);
     const S *src = (const S *)P.buf[parity];
     S *dst = (S *)P.buf[parity ^ 1];
-    March<T, S, SCHEME, false, 2> m(P, src, dst, P.strip * sx);
+    March<T, S, SCHEME, false, 2, REF> m(P, src, dst, P.strip * sx);
     m.run2(j0, j1);
 }
 
@@ -1231,7 +1232,7 @@ __global__ __launch_bounds__(256) void step2_kernel(StepParams<T> P, int parity,
 // workgroup of two waves per work item, wave 0 advancing the first step and wave 1 the
 // second (March::produce / consume), so each holds one level's rows.  Same layout, same
 // work items and the same bits as step2_kernel.
-template <typename T, typename S, int SCHEME>
+template <typename T, typename S, int SCHEME, bool REF>
 __global__ __launch_bounds__(128) void step2p_kernel(StepParams<T> P, int parity, int rows, int nstrips,
                                                      int nwork) {
     __shared__ T ring[2 * 9 * 64];
@@ -1241,7 +1242,7 @@ __global__ __launch_bounds__(128) void step2p_kernel(StepParams<T> P, int parity
     const int j0 = sy * rows, j1 = min(P.ny, j0 + rows);
     const S *src = (const S *)P.buf[parity];
     S *dst = (S *)P.buf[parity ^ 1];
-    March<T, S, SCHEME, false, 2> m(P, src, dst, P.strip * sx);
+    March<T, S, SCHEME, false, 2, REF> m(P, src, dst, P.strip * sx);
     if (__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) == 0) m.produce(j0, j1, ring);
     else m.consume(j0, j1, ring);
 }
@@ -1253,7 +1254,7 @@ __global__ __launch_bounds__(128) void step2p_kernel(StepParams<T> P, int parity
 // Waves whose rows j0-2 .. j1+1 all lie inside the mesh (or wrap on a periodic y axis) need
 // no ghost rows: they take the rotating march of run2, which refills the x-side ghost lanes
 // where the strip has them; only the row blocks at a non-periodic y side take run2b.
-template <typename T, typename S, int SCHEME>
+template <typename T, typename S, int SCHEME, bool REF>
 __global__ __launch_bounds__(256) void step2b_ptr_kernel(const StepParams<T> *__restrict__ Pp, int parity, int rows,
                                                          int nstrips, int nwork) {
     const StepParams<T> &P = *Pp;
@@ -1266,7 +1267,7 @@ __global__ __launch_bounds__(256) void step2b_ptr_kernel(const StepParams<T> *__
     const S *src = (const S *)P.buf[parity];
     S *dst = (S *)P.buf[parity ^ 1];
     const int x0 = P.strip * sx;
-    March<T, S, SCHEME, true, 2> m(P, src, dst, x0);
+    March<T, S, SCHEME, true, 2, REF> m(P, src, dst, x0);
     const bool inner_y = m.per_y || (j0 >= 2 && j1 <= P.ny - 2);
     if (inner_y) m.run2(j0, j1);
     else m.run2b(j0, j1);
@@ -1276,7 +1277,7 @@ __global__ __launch_bounds__(256) void step2b_ptr_kernel(const StepParams<T> *__
 // (one workgroup of two waves per work item; parameters through a device pointer): row
 // blocks clear of the non-periodic y sides take produce / consume (with the x-side ghost
 // lanes refilled), the others produce_b / consume_b.  The same bits as step2b_ptr_kernel.
-template <typename T, typename S, int SCHEME>
+template <typename T, typename S, int SCHEME, bool REF>
 __global__ __launch_bounds__(128) void step2bp_kernel(const StepParams<T> *__restrict__ Pp, int parity, int rows,
                                                       int nstrips, int nwork) {
     __shared__ T ring[2 * 9 * 64];
@@ -1288,7 +1289,7 @@ __global__ __launch_bounds__(128) void step2bp_kernel(const StepParams<T> *__res
     const S *src = (const S *)P.buf[parity];
     S *dst = (S *)P.buf[parity ^ 1];
     const int x0 = P.strip * sx;
-    March<T, S, SCHEME, true, 2> m(P, src, dst, x0);
+    March<T, S, SCHEME, true, 2, REF> m(P, src, dst, x0);
     const bool inner_y = m.per_y || (j0 >= 2 && j1 <= P.ny - 2);
     const bool producer = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) == 0;
     if (inner_y) {

@@ -316,57 +316,49 @@ StepShape step_shape(const HostCase &h, int rows, int wpb) {
 bool params_by_pointer(int, int, bool bnd) { return bnd; }
 
 // one step per launch
-template <typename T, typename S>
+template <typename T, typename S, bool REF>
 void *step_fn(int scheme, bool bnd) {
     if (bnd) {
-        return scheme == SCHEME_BKG ? (void *)step_ptr_kernel<T, S, SCHEME_BKG>
-                                    : (void *)step_ptr_kernel<T, S, SCHEME_DUGKS>;
+        return scheme == SCHEME_BKG ? (void *)step_ptr_kernel<T, S, SCHEME_BKG, REF>
+                                    : (void *)step_ptr_kernel<T, S, SCHEME_DUGKS, REF>;
     }
-    return scheme == SCHEME_BKG ? (void *)step_kernel<T, S, SCHEME_BKG, false>
-                                : (void *)step_kernel<T, S, SCHEME_DUGKS, false>;
+    return scheme == SCHEME_BKG ? (void *)step_kernel<T, S, SCHEME_BKG, false, REF>
+                                : (void *)step_kernel<T, S, SCHEME_DUGKS, false, REF>;
 }
-template <typename T, typename S>
+template <typename T, typename S, bool REF>
 void *step2_fn(int scheme, bool bnd) {
     if (bnd) {
-        return scheme == SCHEME_BKG ? (void *)step2b_ptr_kernel<T, S, SCHEME_BKG>
-                                    : (void *)step2b_ptr_kernel<T, S, SCHEME_DUGKS>;
+        return scheme == SCHEME_BKG ? (void *)step2b_ptr_kernel<T, S, SCHEME_BKG, REF>
+                                    : (void *)step2b_ptr_kernel<T, S, SCHEME_DUGKS, REF>;
     }
-    return scheme == SCHEME_BKG ? (void *)step2_kernel<T, S, SCHEME_BKG> : (void *)step2_kernel<T, S, SCHEME_DUGKS>;
+    return scheme == SCHEME_BKG ? (void *)step2_kernel<T, S, SCHEME_BKG, REF>
+                                : (void *)step2_kernel<T, S, SCHEME_DUGKS, REF>;
 }
 // two steps per launch, a pair of waves per work item (bnd: some side is not periodic;
 // that form reads its parameters through the device copy)
-template <typename T, typename S>
+template <typename T, typename S, bool REF>
 void *step2p_fn(int scheme, bool bnd) {
     if (bnd)
-        return scheme == SCHEME_BKG ? (void *)step2bp_kernel<T, S, SCHEME_BKG> : (void *)step2bp_kernel<T, S, SCHEME_DUGKS>;
-    return scheme == SCHEME_BKG ? (void *)step2p_kernel<T, S, SCHEME_BKG> : (void *)step2p_kernel<T, S, SCHEME_DUGKS>;
+        return scheme == SCHEME_BKG ? (void *)step2bp_kernel<T, S, SCHEME_BKG, REF>
+                                    : (void *)step2bp_kernel<T, S, SCHEME_DUGKS, REF>;
+    return scheme == SCHEME_BKG ? (void *)step2p_kernel<T, S, SCHEME_BKG, REF>
+                                : (void *)step2p_kernel<T, S, SCHEME_DUGKS, REF>;
 }
-void *step2p_fn_variant(int variant, int scheme, bool bnd) {
-    switch (variant) {
-    case V_F64: return step2p_fn<double, double>(scheme, bnd);
-    case V_F32: return step2p_fn<float, float>(scheme, bnd);
-    case V_BF16: return step2p_fn<float, __bf16>(scheme, bnd);
-    default: return step2p_fn<float, _Float16>(scheme, bnd);
+// The kernel of a variant; ref: the FP32 forms with the reference-velocity terms (a
+// reference velocity is set), else without them.  FP64 has none.
+#define LBFV_PICK(FN, variant, ref, ...)                                                        \
+    switch (variant) {                                                                        \
+    case V_F64: return FN<double, double, false>(__VA_ARGS__);                                \
+    case V_F32: return ref ? FN<float, float, true>(__VA_ARGS__) : FN<float, float, false>(__VA_ARGS__); \
+    case V_BF16: return ref ? FN<float, __bf16, true>(__VA_ARGS__) : FN<float, __bf16, false>(__VA_ARGS__); \
+    default: return ref ? FN<float, _Float16, true>(__VA_ARGS__) : FN<float, _Float16, false>(__VA_ARGS__); \
     }
-}
+void *step2p_fn_variant(int variant, int scheme, bool bnd, bool ref) { LBFV_PICK(step2p_fn, variant, ref, scheme, bnd) }
 // two steps per launch; bnd: some side is not periodic
-void *step2_fn_variant(int variant, int scheme, bool bnd) {
-    switch (variant) {
-    case V_F64: return step2_fn<double, double>(scheme, bnd);
-    case V_F32: return step2_fn<float, float>(scheme, bnd);
-    case V_BF16: return step2_fn<float, __bf16>(scheme, bnd);
-    default: return step2_fn<float, _Float16>(scheme, bnd);
-    }
-}
+void *step2_fn_variant(int variant, int scheme, bool bnd, bool ref) { LBFV_PICK(step2_fn, variant, ref, scheme, bnd) }
 // bnd: some side is not periodic (ghost cells / walls present)
-void *step_fn_variant(int variant, int scheme, bool bnd) {
-    switch (variant) {
-    case V_F64: return step_fn<double, double>(scheme, bnd);
-    case V_F32: return step_fn<float, float>(scheme, bnd);
-    case V_BF16: return step_fn<float, __bf16>(scheme, bnd);
-    default: return step_fn<float, _Float16>(scheme, bnd);
-    }
-}
+void *step_fn_variant(int variant, int scheme, bool bnd, bool ref) { LBFV_PICK(step_fn, variant, ref, scheme, bnd) }
+#undef LBFV_PICK
 template <typename T, typename S, bool BND>
 void *batch_fn_b(int scheme, bool two, bool pairs) {
     if (two && pairs)
@@ -394,6 +386,8 @@ void *batch_fn_variant(int variant, int scheme, bool bnd, bool two, bool pairs =
 }
 
 bool has_boundary(const HostCase &h) { return !(h.periodic_x() && h.periodic_y()); }
+// the FP32 step kernels with the reference-velocity terms: only while a reference velocity is set
+bool ref_terms(const HostCase &h) { return !is_f64(h.variant) && (h.u0[0] != 0.0 || h.u0[1] != 0.0); }
 
 // Kernel arguments of one step launch, in a form usable by hipLaunchKernel and by
 // graph kernel nodes.
@@ -455,7 +449,7 @@ int default_rows(const HostCase &h, int scheme, int wpb) {
     if (cells >= (1 << 22)) {
         // large meshes: one round of resident waves
         const bool bnd = !(h.periodic_x() && h.periodic_y());
-        auto r = balanced_rows(h, resident_waves(step_fn_variant(h.variant, scheme, bnd), wpb), STRIP1);
+        auto r = balanced_rows(h, resident_waves(step_fn_variant(h.variant, scheme, bnd, ref_terms(h)), wpb), STRIP1);
         if (!r.empty()) return r[0];
         return std::min(64, h.ny);
     }
@@ -618,8 +612,9 @@ bool paired(const lbfv_ctx *c, bool two) { return two && c->pairs; }
 // without non-periodic sides; one wave or a pair of waves per work item) or one
 void *launch_fn(const lbfv_ctx *c, int scheme, bool two) {
     const HostCase &h = c->hc;
-    if (paired(c, two)) return step2p_fn_variant(h.variant, scheme, has_boundary(h));
-    return two ? step2_fn_variant(h.variant, scheme, has_boundary(h)) : step_fn_variant(h.variant, scheme, has_boundary(h));
+    const bool bnd = has_boundary(h), ref = ref_terms(h);
+    if (paired(c, two)) return step2p_fn_variant(h.variant, scheme, bnd, ref);
+    return two ? step2_fn_variant(h.variant, scheme, bnd, ref) : step_fn_variant(h.variant, scheme, bnd, ref);
 }
 // grid and workgroup of a launch: wpb items of one wave per workgroup, or one item of a
 // pair of waves per workgroup
@@ -1542,8 +1537,8 @@ extern "C" int lbfv_autotune(lbfv_ctx *c, int scheme, int32_t trial_steps, const
                 if (r <= h.ny || r == 1) cands.push_back({t, 0, std::min(r, h.ny), w});
             // balanced heights; the two-step kernel holds more registers (fewer resident
             // waves), so its heights of up to 8 rounds are tried
-            void *fn = t == 1 ? step_fn_variant(h.variant, scheme, has_boundary(h))
-                              : step2_fn_variant(h.variant, scheme, has_boundary(h));
+            void *fn = t == 1 ? step_fn_variant(h.variant, scheme, has_boundary(h), ref_terms(h))
+                              : step2_fn_variant(h.variant, scheme, has_boundary(h), ref_terms(h));
             for (int r : balanced_rows(h, resident_waves(fn, w), t == 1 ? STRIP1 : STRIP2, t == 1 ? 4 : 8))
                 cands.push_back({t, 0, r, w});
         }
@@ -1552,7 +1547,7 @@ extern "C" int lbfv_autotune(lbfv_ctx *c, int scheme, int32_t trial_steps, const
     // heights count resident pairs
     for (int r : {1, 2, 4, 8, 16, 32, 64, 128, 256})
         if (r <= h.ny || r == 1) cands.push_back({2, 1, std::min(r, h.ny), 1});
-    for (int r : balanced_rows(h, resident_waves(step2p_fn_variant(h.variant, scheme, has_boundary(h)), 2) / 2,
+    for (int r : balanced_rows(h, resident_waves(step2p_fn_variant(h.variant, scheme, has_boundary(h), ref_terms(h)), 2) / 2,
                                STRIP2, 8))
         cands.push_back({2, 1, r, 1});
     std::sort(cands.begin(), cands.end());

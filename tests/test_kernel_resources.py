@@ -71,8 +71,8 @@ def test_kernel_digest_identifies_the_binary_kernel():
     lib = L._LIB_PATH
     if not os.path.exists(lib):
         pytest.skip("liblbfv.so is not built")
-    head = "_ZN4lbfv13step2p_kernelIddLi0EEEvNS_10StepParamsIT_EEiiii"
-    bkg = "_ZN4lbfv13step2p_kernelIddLi1EEEvNS_10StepParamsIT_EEiiii"
+    head = "_ZN4lbfv13step2p_kernelIddLi0ELb0EEEvNS_10StepParamsIT_EEiiii"
+    bkg = "_ZN4lbfv13step2p_kernelIddLi1ELb0EEEvNS_10StepParamsIT_EEiiii"
     h1, h2, h3 = (codeobj.kernel_isa_sha256(lib, k) for k in (head, head, bkg))
     if h1 is None:
         pytest.skip("ROCm LLVM tools not found")
