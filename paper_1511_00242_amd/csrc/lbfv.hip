@@ -225,7 +225,7 @@ StepParams<T> make_params(const HostCase &h, double ext[4], int scheme = SCHEME_
     for (int s = 0; s < 4; ++s) {
         P.gext[s] = (h.bc[s] == BC_OUTFLOW && h.bcval[s][0] < 0.5) ? (T)0 : P.ext[s];
         if (h.bc[s] == BC_INFLOW) {
-            // the inflow ghost state, with the operations the kernels used to apply per cell
+            // the inflow ghost state: the kernels' equilibrium of (rho, u), formed once here
             const T rho = P.bcv[s][0], ux = P.bcv[s][1], uy = P.bcv[s][2];
             const T mx = kRefVel<T> ? fmaT(rho, ux, -P.m0x) : rho * ux;
             const T my = kRefVel<T> ? fmaT(rho, uy, -P.m0y) : rho * uy;
@@ -313,7 +313,7 @@ StepShape step_shape(const HostCase &h, int rows, int wpb) {
 // Kernels of a mesh with a non-periodic side read their parameters through a device copy
 // (passed by value, the parameters of the longer march with sides spill from the scalar
 // registers); doubly periodic meshes pass them by value.
-bool params_by_pointer(int, int, bool bnd) { return bnd; }
+bool params_by_pointer(bool bnd) { return bnd; }
 
 // one step per launch
 template <typename T, typename S, bool REF>
@@ -669,11 +669,10 @@ int p2b_upload(lbfv_ctx *c, int scheme, const void *p, size_t bytes, const void 
 
 // the arguments of a launch; the kernels that read their parameters through a pointer get
 // the device copy
-int launch_args(lbfv_ctx *c, int scheme, int parity, const double ext[4], bool two, const StepShape &sh,
-                StepArgs &a) {
+int launch_args(lbfv_ctx *c, int scheme, int parity, const double ext[4], const StepShape &sh, StepArgs &a) {
     HostCase &h = c->hc;
     fill_args(h, ext, sh, parity, scheme, a);
-    if (params_by_pointer(h.variant, scheme, has_boundary(h)) || (paired(c, two) && has_boundary(h))) {
+    if (params_by_pointer(has_boundary(h))) {
         const bool f64 = is_f64(h.variant);
         int st = p2b_upload(c, scheme, f64 ? (const void *)&a.pd : (const void *)&a.pf, f64 ? sizeof(a.pd) : sizeof(a.pf),
                             &a.pptr);
@@ -691,7 +690,7 @@ int launch_one(lbfv_ctx *c, int scheme, int parity, const double ext[4], bool tw
     HostCase &h = c->hc;
     StepShape sh = step_shape(h, c->rows, c->wpb);
     StepArgs a;
-    int st = launch_args(c, scheme, parity, ext, two, sh, a);
+    int st = launch_args(c, scheme, parity, ext, sh, a);
     if (st) return st;
     dim3 grid, block;
     launch_dims(c, two, sh, grid, block);
@@ -707,7 +706,7 @@ int build_graph(lbfv_ctx *c, int scheme, int parity0, const double ext[4], bool 
     hipGraphNode_t prev = nullptr;
     for (int s = 0; s < c->gsteps; ++s) {
         StepArgs a;
-        int st = launch_args(c, scheme, (parity0 + s) & 1, ext, two, sh, a);
+        int st = launch_args(c, scheme, (parity0 + s) & 1, ext, sh, a);
         if (st) {
             (void)hipGraphDestroy(g);
             return st;
