@@ -195,14 +195,19 @@ int lbfv_get_tile(const lbfv_ctx *ctx, int32_t *rows, int32_t *waves_per_block);
  * EINVAL unless 0 or 1. */
 int lbfv_set_wave_pairs(lbfv_ctx *ctx, int32_t on);
 int lbfv_get_wave_pairs(const lbfv_ctx *ctx, int32_t *on);
-/* Time steps per launch of the single-case step: 1 or 2.  With 2, each wavefront reads its
+/* Time steps per launch of the single-case step: 1 to 4.  With 2, each wavefront reads its
  * strip of the state once, keeps the intermediate step in registers (ghost cells, wall and
  * symmetry faces of both steps included) and writes the second, so a step moves half the
  * HBM bytes; the result is the same, bit for bit, as two one-step launches (with 16-bit
- * storage the intermediate step is not rounded to 16 bits, so the two differ).  The state
- * moves to a 60-column strip layout (the buffers of lbfv_required_bytes hold either
- * layout).  An odd step count ends with a one-step launch.  EINVAL for another value, or
- * for 2 before all four sides are set. */
+ * storage the intermediate step is not rounded to 16 bits, so the two differ).  With 3 or
+ * 4 (doubly periodic meshes of at least 2 x steps cells per side) each work item is a
+ * chain of that many wavefronts, one per step, handing rows on through LDS: a step moves a
+ * third or a quarter of the bytes, with the same bits as one-step launches.  The state
+ * moves to a strip layout of 64 - 2 x steps columns (the buffers of lbfv_required_bytes
+ * hold every layout).  Steps left over at the end of a call make one launch of fewer
+ * steps; if a side stops being periodic, the next step call moves to 2.  EINVAL for another
+ * value, for 2 to 4 before all four sides are set, or for 3 or 4 on a mesh with a
+ * non-periodic side or too few cells. */
 int lbfv_set_time_block(lbfv_ctx *ctx, int32_t steps);
 int lbfv_get_time_block(const lbfv_ctx *ctx, int32_t *steps);
 /* Reference velocity U0 (physical units) of the deviation storage: the state is stored as

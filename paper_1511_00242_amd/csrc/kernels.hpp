@@ -83,6 +83,7 @@ struct StepParams {
 // width of a state is that of the march that advances it.
 constexpr int STRIP1 = 62;
 constexpr int STRIP2 = 60;
+constexpr int STRIP4 = 56;   // the narrowest strip (four steps per pass); 64 - 2K for K steps
 constexpr int SLOTS = 64;
 __host__ __device__ __forceinline__ int64_t col_slot(int c, int strip) {
     return (int64_t)(c / strip) * SLOTS + c % strip;
@@ -404,7 +405,7 @@ struct March {
         // are refilled at each level, and their faces with the mesh are faces 0 and nx.
         int fE = min(max(col + 1, 0), nx), fW = min(max(col, 0), nx);
         int ci = min(max(col, 0), nx - 1);
-        if (HALO == 2 && per_x) {
+        if (HALO >= 2 && per_x) {
             fW = ccol;
             fE = ccol + 1;
             ci = ccol;
@@ -876,12 +877,12 @@ struct March {
     }
     // producer, level 0 at row k: Pm, P0, Pp = phi rows k-1, k, k+1; S0 = psi row k; Sm
     // receives psi of row k+2 (with phi in Pm) when a next row is needed
-    __device__ __forceinline__ void produce_row(int k, int j0, int j1, T (&Pm)[9], T (&P0)[9], T (&Pp)[9],
+    __device__ __forceinline__ void produce_row(int k, int a, int b, T (&Pm)[9], T (&P0)[9], T (&Pp)[9],
                                                 T (&Sm)[9], T (&S0)[9], T (&fS)[9], S (&R)[9], T *ring, int t) {
-        const bool need_next = k < j1;
+        const bool need_next = k < b;
         load(need_next ? k + 2 : k, R);
         const int r = row_index(k);
-        if (r == 0 && k != j0 - 1) {
+        if (r == 0 && k != a) {
             // row 0 entered across the periodic seam: its south face is face 0
             yface(0, Pm, P0, fS);
             face_mix<1>(fS);
@@ -895,29 +896,35 @@ struct March {
         }
         __syncthreads();
     }
+    // producer of a chain of M + 1 waves: level 0 at rows j0-M .. j1+M-1, each level-1 row
+    // handed on through the ring; M trailing barriers (the rounds in which later waves still
+    // read)
+    template <int M = 1>
     __device__ __forceinline__ void produce(int j0, int j1, T *ring) {
+        const int a = j0 - M, b = j1 + M - 1;
         T PA[9], PB[9], PC[9], SA[9], SB[9], SC[9], fS[9];
         S R[9], R1[9], R2[9];
-        load(j0 - 2, R);
-        load(j0 - 1, R1);
-        load(j0, R2);
+        load(a - 1, R);
+        load(a, R1);
+        load(a + 1, R2);
         cell(R, PA, SA);
         ghost_x(PA);
         cell(R1, PB, SB);
         ghost_x(PB);
         cell(R2, PC, SC);
         ghost_x(PC);
-        yface(row_index(j0 - 1), PA, PB, fS);
+        yface(row_index(a), PA, PB, fS);
         face_mix<1>(fS);
         int t = 0;
-        for (int k = j0 - 1; k <= j1; k += 3) {
-            produce_row(k, j0, j1, PA, PB, PC, SA, SB, fS, R, ring, t++);
-            if (k + 1 > j1) break;
-            produce_row(k + 1, j0, j1, PB, PC, PA, SB, SC, fS, R, ring, t++);
-            if (k + 2 > j1) break;
-            produce_row(k + 2, j0, j1, PC, PA, PB, SC, SA, fS, R, ring, t++);
+        for (int k = a; k <= b; k += 3) {
+            produce_row(k, a, b, PA, PB, PC, SA, SB, fS, R, ring, t++);
+            if (k + 1 > b) break;
+            produce_row(k + 1, a, b, PB, PC, PA, SB, SC, fS, R, ring, t++);
+            if (k + 2 > b) break;
+            produce_row(k + 2, a, b, PC, PA, PB, SC, SA, fS, R, ring, t++);
         }
-        __syncthreads();   // the consumer's round for row j1
+#pragma unroll
+        for (int i = 0; i < M; ++i) __syncthreads();
     }
     // consumer, the level-1 row k from the ring: Qm2, Qm1 = level-1 phi rows k-2, k-1; Qk,
     // Uk receive phi / psi of row k; Um1 = psi row k-1; gS = level-1 y-face values south of
@@ -938,10 +945,15 @@ struct March {
         }
         __syncthreads();
     }
+    // the last wave of a chain of K waves (K = 2: the pair): level K-1 rows j0-1 .. j1 from the
+    // ring, level K rows j0 .. j1-1 stored.  Its first row was written in round 3K-6 (round
+    // parity t), so it passes 3K-5 barriers first.
+    template <int K = 2>
     __device__ __forceinline__ void consume(int j0, int j1, const T *ring) {
         T QA[9], QB[9], QC[9], UA[9], UB[9], UC[9], gS[9];
-        __syncthreads();   // the producer's round for row j0 - 1
-        int t = 0;
+#pragma unroll
+        for (int i = 0; i < 3 * K - 5; ++i) __syncthreads();
+        int t = 3 * (K - 2);
         for (int k = j0 - 1; k <= j1; k += 3) {
             consume_row(k, j0, QB, QC, QA, UC, UA, gS, ring, t++);
             if (k + 1 > j1) break;
@@ -949,6 +961,54 @@ struct March {
             if (k + 2 > j1) break;
             consume_row(k + 2, j0, QA, QB, QC, UB, UC, gS, ring, t++);
         }
+    }
+
+    // ---- K steps per pass on a doubly periodic mesh (K >= 3, HALO = K): a chain of K waves,
+    // wave w advancing level w.  Wave 0 is the producer above (margin K-1), wave K-1 the
+    // consumer; a middle wave w receives the level-w rows a-1 .. b+1 from ring w-1, one per
+    // round, and hands the level-(w+1) rows a .. b (a = j0-(K-1-w), b = j1-1+(K-1-w)) on
+    // through ring w.  Round r ends with one workgroup barrier in every wave; a row written in
+    // round r (slot r & 1) is read in round r+1, and the writer's next use of that slot is
+    // in round r+2.  Wave 0 writes its i-th row in round i, wave w its j-th in round j + 3w,
+    // so wave w reads its i-th row in round i + 3w - 2: it passes 3w-2 barriers before its
+    // first row and K-w-1 after its last, and every wave passes j1 - j0 + 3K - 3.  Each
+    // update is the one-step march's arithmetic on the same values: the bits of K one-step
+    // launches.
+    __device__ __forceinline__ void middle_row(int k, int a, T (&Qm2)[9], T (&Qm1)[9], T (&Qk)[9], T (&Um1)[9],
+                                               T (&Uk)[9], T (&gS)[9], const T *in, T *out, int t) {
+        T v[9];
+        ring_get(in, t & 1, v);
+        cell_t(v, Qk, Uk);
+        if (k == a) {
+            yface(row_index(a), Qm1, Qk, gS);   // face south of row a
+            face_mix<1>(gS);
+        } else if (k > a) {
+            const int r = row_index(k - 1);
+            if (r == 0 && k - 1 != a) {
+                // row 0 entered across the periodic seam: its south face is face 0
+                yface(0, Qm2, Qm1, gS);
+                face_mix<1>(gS);
+            }
+            T w[9];
+            advance(r, Qm2, Qm1, Qk, Um1, gS, w);   // the next level of row k-1
+            ring_put(out, (t + 1) & 1, w);
+        }
+        __syncthreads();
+    }
+    template <int K>
+    __device__ __forceinline__ void middle(int j0, int j1, int w, const T *in, T *out) {
+        const int a = j0 - (K - 1 - w), b = j1 - 1 + (K - 1 - w);
+        T QA[9], QB[9], QC[9], UA[9], UB[9], UC[9], gS[9];
+        for (int i = 0; i < 3 * w - 2; ++i) __syncthreads();
+        int t = 3 * (w - 1);
+        for (int k = a - 1; k <= b + 1; k += 3) {
+            middle_row(k, a, QB, QC, QA, UC, UA, gS, in, out, t++);
+            if (k + 1 > b + 1) break;
+            middle_row(k + 1, a, QC, QA, QB, UA, UB, gS, in, out, t++);
+            if (k + 2 > b + 1) break;
+            middle_row(k + 2, a, QA, QB, QC, UB, UC, gS, in, out, t++);
+        }
+        for (int i = 0; i < K - w - 1; ++i) __syncthreads();
     }
 
     // the sides of the south face of the mesh (wall, symmetry, wall segment)
@@ -1245,6 +1305,28 @@ __global__ __launch_bounds__(128) void step2p_kernel(StepParams<T> P, int parity
     March<T, S, SCHEME, false, 2, REF> m(P, src, dst, P.strip * sx);
     if (__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) == 0) m.produce(j0, j1, ring);
     else m.consume(j0, j1, ring);
+}
+
+// K time steps per launch on a doubly periodic mesh (K = 3 or 4; strips of 64 - 2K columns),
+// a chain of K waves per work item, one per time level (March::produce / middle / consume).
+// Each wave holds one level's rows; the levels pass through two-slot rings in LDS.  The same
+// bits as K one-step launches.
+template <typename T, typename S, int SCHEME, bool REF, int K>
+__global__ __launch_bounds__(64 * K) void stepc_kernel(StepParams<T> P, int parity, int rows, int nstrips,
+                                                       int nwork) {
+    constexpr int RING = 2 * 9 * 64;
+    __shared__ T ring[(K - 1) * RING];
+    const int w = xcd_block();
+    if (w >= nwork) return;   // the whole workgroup: all waves pass the same barriers
+    const int sx = w % nstrips, sy = w / nstrips;
+    const int j0 = sy * rows, j1 = min(P.ny, j0 + rows);
+    const S *src = (const S *)P.buf[parity];
+    S *dst = (S *)P.buf[parity ^ 1];
+    March<T, S, SCHEME, false, K, REF> m(P, src, dst, P.strip * sx);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (wave == 0) m.template produce<K - 1>(j0, j1, ring);
+    else if (wave == K - 1) m.template consume<K>(j0, j1, ring + (K - 2) * RING);
+    else m.template middle<K>(j0, j1, wave, ring + (wave - 1) * RING, ring + wave * RING);
 }
 
 // Two time steps per launch on a mesh with a non-periodic side (60-column strip layout),

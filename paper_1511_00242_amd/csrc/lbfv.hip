@@ -37,7 +37,7 @@ struct HostCase {
     double rho0 = 0.0;        // 0 for native storage
     double u0[2] = {0.0, 0.0};   // reference velocity of the deviation storage (physical units)
     int strip = STRIP1;       // output columns per 64-slot block of the current state
-    int tblock = 1;           // time steps per launch of the single-case step (1 or 2)
+    int tblock = 1;           // time steps per launch of the single-case step (1 to 4)
     int64_t pitch = 0, plane = 0;
     size_t esize = 8;
     void *buf[2] = {nullptr, nullptr};
@@ -47,8 +47,8 @@ struct HostCase {
     double *d_dx = nullptr, *d_dy = nullptr; // cell sizes (FP64) for volumes
     bool metrics_dirty = true;
 
-    // buffers fit the state in either strip layout
-    size_t buffer_bytes() const { return (size_t)padded_pitch(nx, STRIP2) * ny * 9 * esize; }
+    // buffers fit the state in every strip layout (the narrowest strip pads most)
+    size_t buffer_bytes() const { return (size_t)padded_pitch(nx, STRIP4) * ny * 9 * esize; }
     void set_strip(int w) {
         strip = w;
         pitch = padded_pitch(nx, w);
@@ -81,9 +81,9 @@ struct lbfv_ctx {
     int64_t steps = 0, steps_at_check = 0;
     int rows = 0, wpb = 4;
     int pairs = 0;                   // two steps per launch, periodic mesh: a pair of waves per item
-    // graphs of `gsteps` launches, per scheme (+4 for two steps per launch) and starting buffer
+    // graphs of `gsteps` launches, per scheme (+4 per further step per launch) and starting buffer
     int gsteps = 32;
-    hipGraphExec_t gexec[8][2] = {};
+    hipGraphExec_t gexec[16][2] = {};
     // reductions
     double *d_partial = nullptr, *d_out = nullptr, *h_out = nullptr, *d_uprev = nullptr;
     int red_blocks = 0;
@@ -344,6 +344,15 @@ void *step2p_fn(int scheme, bool bnd) {
     return scheme == SCHEME_BKG ? (void *)step2p_kernel<T, S, SCHEME_BKG, REF>
                                 : (void *)step2p_kernel<T, S, SCHEME_DUGKS, REF>;
 }
+// K steps per launch on a doubly periodic mesh, a chain of K waves per work item (K = 3, 4)
+template <typename T, typename S, bool REF>
+void *stepc_fn(int scheme, int K) {
+    if (K == 3)
+        return scheme == SCHEME_BKG ? (void *)stepc_kernel<T, S, SCHEME_BKG, REF, 3>
+                                    : (void *)stepc_kernel<T, S, SCHEME_DUGKS, REF, 3>;
+    return scheme == SCHEME_BKG ? (void *)stepc_kernel<T, S, SCHEME_BKG, REF, 4>
+                                : (void *)stepc_kernel<T, S, SCHEME_DUGKS, REF, 4>;
+}
 // The kernel of a variant; ref: the FP32 forms with the reference-velocity terms (a
 // reference velocity is set), else without them.  FP64 has none.
 #define LBFV_PICK(FN, variant, ref, ...)                                                        \
@@ -358,6 +367,8 @@ void *step2p_fn_variant(int variant, int scheme, bool bnd, bool ref) { LBFV_PICK
 void *step2_fn_variant(int variant, int scheme, bool bnd, bool ref) { LBFV_PICK(step2_fn, variant, ref, scheme, bnd) }
 // bnd: some side is not periodic (ghost cells / walls present)
 void *step_fn_variant(int variant, int scheme, bool bnd, bool ref) { LBFV_PICK(step_fn, variant, ref, scheme, bnd) }
+// K = 3, 4 steps per launch (doubly periodic meshes only)
+void *stepc_fn_variant(int variant, int scheme, int K, bool ref) { LBFV_PICK(stepc_fn, variant, ref, scheme, K) }
 #undef LBFV_PICK
 template <typename T, typename S, bool BND>
 void *batch_fn_b(int scheme, bool two, bool pairs) {
@@ -606,22 +617,24 @@ void current_ext(const HostCase &h, double ext[4]) {
 }
 
 // a launch of two steps with the pair-of-waves form
-bool paired(const lbfv_ctx *c, bool two) { return two && c->pairs; }
+bool paired(const lbfv_ctx *c, int tb) { return tb == 2 && c->pairs; }
 
-// the step kernel of a launch: two steps per launch (in the 60-column layout; with or
-// without non-periodic sides; one wave or a pair of waves per work item) or one
-void *launch_fn(const lbfv_ctx *c, int scheme, bool two) {
+// the step kernel of a launch of tb steps: a chain of tb waves per work item (tb = 3, 4;
+// doubly periodic meshes), two steps (in a strip layout of 60 columns or fewer; with or
+// without non-periodic sides; one wave or a pair of waves per work item), or one
+void *launch_fn(const lbfv_ctx *c, int scheme, int tb) {
     const HostCase &h = c->hc;
     const bool bnd = has_boundary(h), ref = ref_terms(h);
-    if (paired(c, two)) return step2p_fn_variant(h.variant, scheme, bnd, ref);
-    return two ? step2_fn_variant(h.variant, scheme, bnd, ref) : step_fn_variant(h.variant, scheme, bnd, ref);
+    if (tb >= 3) return stepc_fn_variant(h.variant, scheme, tb, ref);
+    if (paired(c, tb)) return step2p_fn_variant(h.variant, scheme, bnd, ref);
+    return tb == 2 ? step2_fn_variant(h.variant, scheme, bnd, ref) : step_fn_variant(h.variant, scheme, bnd, ref);
 }
 // grid and workgroup of a launch: wpb items of one wave per workgroup, or one item of a
-// pair of waves per workgroup
-void launch_dims(const lbfv_ctx *c, bool two, const StepShape &sh, dim3 &grid, dim3 &block) {
-    if (paired(c, two)) {
+// pair (a chain) of waves per workgroup
+void launch_dims(const lbfv_ctx *c, int tb, const StepShape &sh, dim3 &grid, dim3 &block) {
+    if (tb >= 3 || paired(c, tb)) {
         grid = dim3(sh.nwork);
-        block = dim3(128);
+        block = dim3(64 * tb);
     } else {
         grid = dim3(sh.nblocks);
         block = dim3(64 * sh.wpb);
@@ -686,19 +699,19 @@ int launch_args(lbfv_ctx *c, int scheme, int parity, const double ext[4], const 
     return LBFV_OK;
 }
 
-int launch_one(lbfv_ctx *c, int scheme, int parity, const double ext[4], bool two = false) {
+int launch_one(lbfv_ctx *c, int scheme, int parity, const double ext[4], int tb = 1) {
     HostCase &h = c->hc;
     StepShape sh = step_shape(h, c->rows, c->wpb);
     StepArgs a;
     int st = launch_args(c, scheme, parity, ext, sh, a);
     if (st) return st;
     dim3 grid, block;
-    launch_dims(c, two, sh, grid, block);
-    HIPCHK(hipLaunchKernel(launch_fn(c, scheme, two), grid, block, a.args, 0, c->stream));
+    launch_dims(c, tb, sh, grid, block);
+    HIPCHK(hipLaunchKernel(launch_fn(c, scheme, tb), grid, block, a.args, 0, c->stream));
     return LBFV_OK;
 }
 
-int build_graph(lbfv_ctx *c, int scheme, int parity0, const double ext[4], bool two = false) {
+int build_graph(lbfv_ctx *c, int scheme, int parity0, const double ext[4], int tb = 1) {
     HostCase &h = c->hc;
     StepShape sh = step_shape(h, c->rows, c->wpb);
     hipGraph_t g;
@@ -713,8 +726,8 @@ int build_graph(lbfv_ctx *c, int scheme, int parity0, const double ext[4], bool 
         }
         hipKernelNodeParams kp;
         memset(&kp, 0, sizeof(kp));
-        kp.func = launch_fn(c, scheme, two);
-        launch_dims(c, two, sh, kp.gridDim, kp.blockDim);
+        kp.func = launch_fn(c, scheme, tb);
+        launch_dims(c, tb, sh, kp.gridDim, kp.blockDim);
         kp.sharedMemBytes = 0;
         kp.kernelParams = a.args;
         kp.extra = nullptr;
@@ -726,7 +739,7 @@ int build_graph(lbfv_ctx *c, int scheme, int parity0, const double ext[4], bool 
         }
         prev = node;
     }
-    hipError_t e = hipGraphInstantiate(&c->gexec[scheme + (two ? 4 : 0)][parity0], g, nullptr, nullptr, 0);
+    hipError_t e = hipGraphInstantiate(&c->gexec[scheme + 4 * (tb - 1)][parity0], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return c->fail(LBFV_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     return LBFV_OK;
@@ -838,11 +851,16 @@ int do_steps(lbfv_ctx *c, int scheme, int32_t n) {
     double ext[4];
     st = ensure_metrics(c, ext);
     if (st) return st;
+    if (h.tblock >= 3 && has_boundary(h)) {
+        // a side stopped being periodic: the chains of waves have no ghost cells, so the
+        // mesh continues with two steps per launch
+        if ((st = lbfv_set_time_block(c, 2))) return st;
+    }
     current_ext(h, ext);
     if (c->rows <= 0) c->rows = default_rows(h, scheme, c->wpb);
-    // two steps per launch when the time block is 2; an odd step is a one-step launch
-    const bool two = h.tblock == 2;
-    const int per = two ? 2 : 1;
+    // tblock steps per launch; the steps left over make one launch of fewer steps, in the
+    // same strip layout (every narrower march fits a wider halo's strip)
+    const int per = h.tblock;
     while (n > 0) {
         int seg = n;
         if (c->check_every > 0) {
@@ -851,9 +869,9 @@ int do_steps(lbfv_ctx *c, int scheme, int32_t n) {
         }
         int left = seg;
         while (left >= per * c->gsteps) {
-            hipGraphExec_t &g = c->gexec[scheme + (two ? 4 : 0)][h.cur];
+            hipGraphExec_t &g = c->gexec[scheme + 4 * (per - 1)][h.cur];
             if (!g) {
-                st = build_graph(c, scheme, h.cur, ext, two);
+                st = build_graph(c, scheme, h.cur, ext, per);
                 if (st) return st;
             }
             HIPCHK(hipGraphLaunch(g, c->stream));
@@ -861,12 +879,12 @@ int do_steps(lbfv_ctx *c, int scheme, int32_t n) {
             left -= per * c->gsteps;
         }
         for (; left >= per; left -= per) {
-            st = launch_one(c, scheme, h.cur, ext, two);
+            st = launch_one(c, scheme, h.cur, ext, per);
             if (st) return st;
             h.cur ^= 1;
         }
         if (left > 0) {
-            st = launch_one(c, scheme, h.cur, ext);
+            st = launch_one(c, scheme, h.cur, ext, left);
             if (st) return st;
             h.cur ^= 1;
         }
@@ -1333,10 +1351,14 @@ int lbfv_residual(lbfv_ctx *c, double *r) {
 int lbfv_set_time_block(lbfv_ctx *c, int32_t steps) {
     if (!c) return LBFV_EINVAL;
     HostCase &h = c->hc;
-    if (steps != 1 && steps != 2) return c->fail(LBFV_EINVAL, "lbfv_set_time_block: steps must be 1 or 2");
-    if (steps == 2 && !h.sides_set())
+    if (steps < 1 || steps > 4) return c->fail(LBFV_EINVAL, "lbfv_set_time_block: steps must be 1 to 4");
+    if (steps >= 2 && !h.sides_set())
         return c->fail(LBFV_EINVAL, "lbfv_set_time_block: set all four sides first");
-    const int w = steps == 2 ? STRIP2 : STRIP1;
+    if (steps >= 3 && has_boundary(h))
+        return c->fail(LBFV_EINVAL, "lbfv_set_time_block: 3 or 4 steps per launch need a doubly periodic mesh");
+    if (steps >= 3 && (h.nx < 2 * steps || h.ny < 2 * steps))
+        return c->fail(LBFV_EINVAL, "lbfv_set_time_block: 3 or 4 steps per launch need at least 2 x steps cells per side");
+    const int w = SLOTS - 2 * steps;   // 62, 60, 58 or 56 output columns per strip
     if (w != h.strip) {
         if (c->has_state) {
             // move the current state into the other buffer in the new layout
@@ -1465,7 +1487,7 @@ bool cache_lookup(const char *path, const std::string &key, int &rows, int &wpb,
             int r, w, k = 1, pr = 0;
             double m;
             if (t >> r >> w >> m) {
-                if (!(t >> k) || (k != 1 && k != 2)) k = 1;
+                if (!(t >> k) || k < 1 || k > 4) k = 1;
                 if (!(t >> pr) || (pr != 0 && pr != 1)) pr = 0;
                 rows = r;
                 wpb = w;
@@ -1499,7 +1521,9 @@ extern "C" int lbfv_autotune(lbfv_ctx *c, int scheme, int32_t trial_steps, const
     const std::string key = tune_key(h, scheme);
     int rows, wpb, tb, pairs;
     double ms;
-    if (cache_lookup(path, key, rows, wpb, ms, tb, pairs)) {
+    // (an entry of the same size class whose time block this mesh cannot take is ignored)
+    if (cache_lookup(path, key, rows, wpb, ms, tb, pairs) &&
+        (tb < 3 || (!has_boundary(h) && std::min(h.nx, h.ny) >= 2 * tb))) {
         int st = lbfv_set_time_block(c, tb);
         if (st) return st;
         c->rows = std::min(rows, h.ny);
@@ -1549,6 +1573,16 @@ extern "C" int lbfv_autotune(lbfv_ctx *c, int scheme, int32_t trial_steps, const
     for (int r : balanced_rows(h, resident_waves(step2p_fn_variant(h.variant, scheme, has_boundary(h), ref_terms(h)), 2) / 2,
                                STRIP2, 8))
         cands.push_back({2, 1, r, 1});
+    // three and four steps per launch on doubly periodic meshes: a chain of waves per item
+    // (one workgroup each); the balanced heights count resident chains
+    if (!has_boundary(h))
+        for (int t : {3, 4}) {
+            if (std::min(h.nx, h.ny) < 2 * t) continue;
+            for (int r : {1, 2, 4, 8, 16, 32, 64, 128, 256})
+                if (r <= h.ny || r == 1) cands.push_back({t, 0, std::min(r, h.ny), 1});
+            void *fn = stepc_fn_variant(h.variant, scheme, t, ref_terms(h));
+            for (int r : balanced_rows(h, resident_waves(fn, t) / t, SLOTS - 2 * t, 8)) cands.push_back({t, 0, r, 1});
+        }
     std::sort(cands.begin(), cands.end());
     cands.erase(std::unique(cands.begin(), cands.end()), cands.end());
     for (const auto &cand : cands) {

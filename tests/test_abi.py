@@ -94,8 +94,11 @@ def test_state_errors_before_any_device_work():
     assert L.lib().lbfv_set_inflow_eq(ctx.h, 0, -1.0, 0.0, 0.0) == L.LBFV_EINVAL
     assert L.lib().lbfv_set_periodic(ctx.h, 5) == L.LBFV_EINVAL
     assert L.lib().lbfv_set_tile(ctx.h, 8, 3) == L.LBFV_EINVAL
-    assert L.lib().lbfv_set_time_block(ctx.h, 3) == L.LBFV_EINVAL
-    L._check(L.lib().lbfv_set_time_block(ctx.h, 2), ctx.h)      # periodic, no state yet
+    assert L.lib().lbfv_set_time_block(ctx.h, 5) == L.LBFV_EINVAL
+    assert L.lib().lbfv_set_time_block(ctx.h, 0) == L.LBFV_EINVAL
+    assert L.lib().lbfv_set_time_block(ctx.h, 4) == L.LBFV_EINVAL   # 8 x 6 mesh: 4 steps need 8 per side
+    L._check(L.lib().lbfv_set_time_block(ctx.h, 3), ctx.h)      # periodic, no state yet
+    L._check(L.lib().lbfv_set_time_block(ctx.h, 2), ctx.h)
     L._check(L.lib().lbfv_set_time_block(ctx.h, 1), ctx.h)
     assert L.lib().lbfv_set_wave_pairs(ctx.h, 2) == L.LBFV_EINVAL
     assert ctx.get_wave_pairs() is False
@@ -124,6 +127,9 @@ def test_state_errors_before_any_device_work():
     # replacing one side of a periodic axis leaves the other side unset
     L._check(L.lib().lbfv_set_wall(ctx.h, L.LBFV_WEST, 0.0, 0.0), ctx.h)
     assert L.lib().dugks_step(ctx.h, 1) == L.LBFV_ESTATE
+    L._check(L.lib().lbfv_set_wall(ctx.h, L.LBFV_EAST, 0.0, 0.0), ctx.h)
+    assert L.lib().lbfv_set_time_block(ctx.h, 3) == L.LBFV_EINVAL   # walls: at most two steps per launch
+    L._check(L.lib().lbfv_set_time_block(ctx.h, 2), ctx.h)
     # the reference velocity belongs to deviation storage
     assert L.lib().lbfv_set_reference_velocity(ctx.h, 0.1, 0.0) == L.LBFV_EINVAL
     ctx.close()

@@ -593,22 +593,29 @@ def _periodic_workload(nx, ny, seed):
     return I.Workload(f"periodic{nx}x{ny}", xf, yf, 0.01, I.cfl_dt(xf, yf, 0.6), ["periodic"] * 4, rho, ux, uy)
 
 
-@pytest.mark.parametrize("nx,ny", [(130, 37), (2, 2), (3, 5), (61, 3), (120, 4), (181, 9)])
+@pytest.mark.parametrize("nx,ny", [(130, 37), (2, 2), (3, 5), (61, 3), (120, 4), (181, 9), (6, 6), (8, 8),
+                                   (56, 8), (57, 11), (113, 16)])
 def test_two_steps_per_launch_equal_two_launches(nx, ny):
     """lbfv_set_time_block(2) on stretched doubly periodic meshes (ragged 60-column strips,
     meshes narrower than one strip), with one wave and with a pair of waves per work item
-    (lbfv_set_wave_pairs): the same bits as one-step launches for every scheme, FP64, FP32
-    and FP16 deviation storage, odd step counts and graph replays included, and the
-    oracle's result in FP64."""
+    (lbfv_set_wave_pairs), and lbfv_set_time_block(3) and (4), the chains of three and four
+    waves (58- and 56-column strips, meshes down to 2 x steps cells per side): the same bits
+    as one-step launches for every scheme, FP64 and FP32 deviation storage, step counts that
+    leave every remainder and graph replays included, and the oracle's result in FP64.  FP16
+    deviation storage: the one-wave and pair forms of two steps agree."""
     w = _periodic_workload(nx, ny, nx * 7 + ny)
     ora = oracle_case(w, 2)
     f0 = perturbed_state(ora, w, 31)
+    chains = [(tb, False) for tb in (3, 4) if min(nx, ny) >= 2 * tb]
     for scheme, oscheme in SCHEMES + [(L.LBFV_CENTRAL, O.CENTRAL), (L.LBFV_UPWIND, O.UPWIND)]:
         for compute, storage in ((L.LBFV_FP64, L.LBFV_STORE_NATIVE), (L.LBFV_FP32, L.LBFV_STORE_DEV_FP32),
                                  (L.LBFV_FP32, L.LBFV_STORE_DEV_FP16)):
             for n, tile in ((41, (4, 1)), (150, (7, 2))):
                 outs = []
-                for tb, pairs in ((1, False), (2, False), (2, True)):
+                forms = [(1, False), (2, False), (2, True)]
+                if storage != L.LBFV_STORE_DEV_FP16:
+                    forms += chains
+                for tb, pairs in forms:
                     with L.Context(w.xf, w.yf, w.tau, w.dt, bcs=w.bcs, compute=compute, storage=storage) as ctx:
                         ctx.set_f(f0)
                         ctx.set_time_block(tb)
@@ -625,8 +632,10 @@ def test_two_steps_per_launch_equal_two_launches(nx, ny):
                     continue
                 assert np.array_equal(outs[0], outs[1]), (nx, ny, scheme, compute, n)
                 assert np.array_equal(outs[0], outs[2]), (nx, ny, scheme, compute, n, "pairs")
+                for (tb, _), g in zip(chains, outs[3:]):
+                    assert np.array_equal(outs[0], g), (nx, ny, scheme, compute, n, "chain", tb)
                 if compute == L.LBFV_FP64 and n == 41:
-                    assert rel(outs[2], ora.run(f0, oscheme, n)) < TOL64
+                    assert rel(outs[-1], ora.run(f0, oscheme, n)) < TOL64
 
 
 def _side_sets(nx):
@@ -726,19 +735,23 @@ def test_time_block_switch_keeps_state_and_falls_back_off_periodic():
     f0 = perturbed_state(ora, w, 37)
     with L.Context(w.xf, w.yf, w.tau, w.dt, bcs=w.bcs) as ctx:
         ctx.set_f(f0)
-        for tb in (2, 1, 2):
+        for tb in (2, 1, 4, 3, 2, 4):
             ctx.set_time_block(tb)
             assert np.array_equal(ctx.get_f(), f0)
         ctx.dugks_step(10)
         ctx.set_time_block(1)
         ctx.dugks_step(10)
+        ctx.set_time_block(3)
+        ctx.dugks_step(5)
         ctx.set_time_block(2)
-        ctx.dugks_step(11)
+        ctx.dugks_step(6)
         g = ctx.get_f()
         r, u, v = ctx.moments()
         ro, uo, vo = ora.moments(ora.run(f0, O.DUGKS, 31))
         assert rel(g, ora.run(f0, O.DUGKS, 31)) < TOL64 and rel(u, uo) < TOL64
-        # a non-periodic side: the same state is advanced by the two-step form with sides
+        # a non-periodic side: the same state is advanced by the two-step form with sides;
+        # from four steps per launch the next step call moves to two
+        ctx.set_time_block(4)
         ctx.set_sides([("wall", 0.0, 0.0), ("outflow", 0), "periodic", "periodic"])
         ctx.bkg_step(7)
         assert ctx.get_time_block() == 2
