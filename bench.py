@@ -26,10 +26,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-HEADLINE_TILE = (142, 1)        # rows per block, waves per block of the timed 4096^2 step, and
-HEADLINE_TIME_BLOCK = 2        # steps per launch (fixed so that the committed counter profile
+HEADLINE_TILE = (110, 1)        # rows per block, waves per block of the timed 4096^2 step, and
+HEADLINE_TIME_BLOCK = 4        # steps per launch (fixed so that the committed counter profile
                                # describes the same launches)
-HEADLINE_PAIRS = 1             # two steps per launch: one wave (0) or a pair of waves (1) per item
+HEADLINE_PAIRS = 0             # two steps per launch: one wave (0) or a pair of waves (1) per item
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_dugks_fp64_taylor_green_4096.txt")
 BYTES = {"f64": 144, "f32": 72, "bf16": 36, "f16": 36}   # algorithmic bytes per cell-step (9 reads + 9 writes)
 
@@ -54,7 +54,7 @@ def parse():
     p.add_argument("--batch-shape", default="",
                    help="time_block,rows,wave_per_item[,wave_pairs] (0/1) of the batch (skips its autotuner)")
     p.add_argument("--time-block", type=int, default=HEADLINE_TIME_BLOCK,
-                   help="steps per launch with --tile on doubly periodic meshes (1 or 2)")
+                   help="steps per launch with --tile on doubly periodic meshes (1 to 4)")
     p.add_argument("--pairs", type=int, default=HEADLINE_PAIRS,
                    help="with --tile and two steps per launch: a pair of waves per work item (1) or one (0)")
     p.add_argument("--copy-probe-mb", type=int, default=0,
@@ -393,7 +393,7 @@ def boundary_layer_paper(a, stream):
     return out
 
 
-HEADLINE_KERNEL = "_ZN4lbfv13step2p_kernelIddLi0ELb0EEEvNS_10StepParamsIT_EEiiii"   # step2p_kernel<double,double,DUGKS>
+HEADLINE_KERNEL = "_ZN4lbfv12stepc_kernelIddLi0ELb0ELi4EEEvNS_10StepParamsIT_EEiiii"   # stepc_kernel<double,double,DUGKS,4>
 
 
 def kernel_isa_hash():
@@ -664,8 +664,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": traffic_gbs,
                      "traffic_bytes_per_launch": traffic_bytes,
-                     "kernel": (("lbfv::step2p_kernel<double,double,DUGKS>" if head["wave_pairs"]
-                                 else "lbfv::step2_kernel<double,double,DUGKS>") if head["time_block"] == 2
+                     "kernel": (f"lbfv::stepc_kernel<double,double,DUGKS,{head['time_block']}>" if head["time_block"] >= 3
+                                else ("lbfv::step2p_kernel<double,double,DUGKS>" if head["wave_pairs"]
+                                      else "lbfv::step2_kernel<double,double,DUGKS>") if head["time_block"] == 2
                                 else "lbfv::step_kernel<double,double,DUGKS>"),
                      "steps_per_launch": head["time_block"],
                      "kernel_ms": kern["ms_per_step"],

@@ -84,7 +84,12 @@ typedef struct {
  *               (Sec. 2.1, Eq. equilibrium) of a reference state, U0 = 0 unless
  *               lbfv_set_reference_velocity sets it; DEV_* need FP32 compute.
  *   rho0        reference density of the deviation storage.
- *   check_every steps between the FP64 checks (non-finite flag); 0 disables them.
+ *   check_every steps between the non-finite checks; 0 disables them.  A check runs
+ *               at the first launch boundary at or after check_every steps since the
+ *               last one (at most steps-per-launch - 1 steps later) and reads the rest
+ *               direction: a non-finite value in any direction reaches it through the
+ *               cell's density within one step, so the first check made at least one
+ *               step after such a value appears finds it.  lbfv_totals checks all nine.
  *   hip_stream  hipStream_t to run on; NULL = the default stream. */
 typedef struct {
     int32_t compute;

@@ -206,6 +206,31 @@ __global__ __launch_bounds__(RED_BLOCK) void reduce_kernel(StepParams<T> P, int 
     block_sum(v, sh, partial + (int64_t)blockIdx.x * RED_N);
 }
 
+// The periodic non-finite check of the stepping loop.  It reads the rest direction's plane
+// only (1/9 of the state): a non-finite f_a makes its cell's density non-finite, and the
+// cell stage of the next step carries that into every direction of the cell, the rest
+// direction included; so a non-finite value is seen by the first check made at least one
+// step after it appeared.  Counts the cells into partial[block * RED_N + 5] (the other
+// slots 0) for reduce_final_kernel.  Walks the padded row by slots (pads skipped).
+template <typename S>
+__global__ __launch_bounds__(RED_BLOCK) void check_rest_kernel(const S *src, int nx, int ny, int64_t pitch,
+                                                               int strip, double *partial) {
+    __shared__ double sh[RED_N][RED_WAVES];
+    double v[RED_N] = {0, 0, 0, 0, 0, 0};
+    const int slots = (int)padded_pitch(nx, strip);
+    int bad = 0;
+    for (int j = blockIdx.x; j < ny; j += gridDim.x) {
+        const S *row = src + (int64_t)j * pitch;
+        for (int s = threadIdx.x; s < slots; s += blockDim.x) {
+            const int l = s & (SLOTS - 1);
+            const int col = (s / SLOTS) * strip + l;
+            if (l < strip && col < nx) bad += isfinite((double)row[s]) ? 0 : 1;
+        }
+    }
+    v[5] = (double)bad;
+    block_sum(v, sh, partial + (int64_t)blockIdx.x * RED_N);
+}
+
 // compact = 0: out[0..5] as above; compact = 1: out[0..3] = totals[0..2] and the
 // non-finite count (the residual sums are not formed in that mode).
 __global__ __launch_bounds__(RED_BLOCK) void reduce_final_kernel(const double *partial, int nblocks, double *out,

@@ -797,10 +797,41 @@ int poll_check(lbfv_ctx *c, bool wait) {
     return LBFV_OK;
 }
 
+// the check of the stepping loop: the rest-direction plane only (check_rest_kernel)
+int launch_check(lbfv_ctx *c) {
+    int st = ensure_reduction(c);
+    if (st) return st;
+    const HostCase &h = c->hc;
+    const dim3 grid(c->red_blocks), block(RED_BLOCK);
+    switch (h.variant) {
+    case V_F64:
+        hipLaunchKernelGGL(check_rest_kernel<double>, grid, block, 0, c->stream, (const double *)h.buf[h.cur],
+                           h.nx, h.ny, h.pitch, h.strip, c->d_partial);
+        break;
+    case V_F32:
+        hipLaunchKernelGGL(check_rest_kernel<float>, grid, block, 0, c->stream, (const float *)h.buf[h.cur], h.nx,
+                           h.ny, h.pitch, h.strip, c->d_partial);
+        break;
+    case V_BF16:
+        hipLaunchKernelGGL(check_rest_kernel<__bf16>, grid, block, 0, c->stream, (const __bf16 *)h.buf[h.cur],
+                           h.nx, h.ny, h.pitch, h.strip, c->d_partial);
+        break;
+    default:
+        hipLaunchKernelGGL(check_rest_kernel<_Float16>, grid, block, 0, c->stream,
+                           (const _Float16 *)h.buf[h.cur], h.nx, h.ny, h.pitch, h.strip, c->d_partial);
+        break;
+    }
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(RED_BLOCK), 0, c->stream, c->d_partial, c->red_blocks,
+                       c->d_out, 0);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(c->h_out, c->d_out, sizeof(double) * RED_N, hipMemcpyDeviceToHost, c->stream));
+    return LBFV_OK;
+}
+
 int start_check(lbfv_ctx *c) {
     int st = poll_check(c, true);
     if (st) return st;
-    st = launch_reduce(c, 0);
+    st = launch_check(c);
     if (st) return st;
     HIPCHK(hipEventRecord(c->check_event, c->stream));
     c->check_pending = true;
@@ -864,8 +895,11 @@ int do_steps(lbfv_ctx *c, int scheme, int32_t n) {
     while (n > 0) {
         int seg = n;
         if (c->check_every > 0) {
-            const int64_t to_check = c->check_every - (c->steps - c->steps_at_check);
-            seg = (int)std::min<int64_t>(seg, std::max<int64_t>(to_check, 1));
+            // the check comes at the first launch boundary at or after check_every steps,
+            // so that a check never splits a launch of `per` steps into shorter ones
+            int64_t to_check = std::max<int64_t>(c->check_every - (c->steps - c->steps_at_check), 1);
+            to_check = (to_check + per - 1) / per * per;
+            seg = (int)std::min<int64_t>(seg, to_check);
         }
         int left = seg;
         while (left >= per * c->gsteps) {

@@ -57,11 +57,11 @@ def test_no_kernel_uses_scratch_memory(tmp_path):
 
 
 def test_pair_kernels_fit_two_waves_per_simd(tmp_path):
-    # 512 vector registers per SIMD lane: the FP64 pair kernels (the headline and the forms
-    # with sides) must stay at or below 256 so that two waves share a SIMD
+    # 512 vector registers per SIMD lane: the FP64 pair and chain kernels (the headline and
+    # the forms with sides) must stay at or below 256 so that two waves share a SIMD
     md = kernel_metadata(tmp_path)
     for k, v in md.items():
-        if "step2p_kernelIdd" in k or "step2bp_kernelIdd" in k:
+        if "step2p_kernelIdd" in k or "step2bp_kernelIdd" in k or "stepc_kernelIdd" in k:
             assert v["vgpr_count"] <= 256, (k, v)
 
 
