@@ -149,8 +149,10 @@ int lbfv_bind_buffers(lbfv_ctx *ctx, void *dev_a, void *dev_b, size_t bytes);
 int lbfv_required_bytes(const lbfv_ctx *ctx, size_t *bytes_per_buffer);
 
 /* Advance nsteps time steps; asynchronous on the context stream.  Returns EUNSTABLE
- * if an earlier check found a non-finite value, ESTATE if a side is unset or no state
- * has been set. */
+ * if an earlier check found a non-finite value (checks are read without waiting: a
+ * call sees the result of every check the device has finished; the next check, and
+ * lbfv_totals, wait for a pending one), ESTATE if a side is unset or no state has
+ * been set. */
 int dugks_step(lbfv_ctx *ctx, int32_t nsteps);
 int bkg_step(lbfv_ctx *ctx, int32_t nsteps);
 /* Any of the four schemes.  CENTRAL (Eq. cfd1): the face value is f^n interpolated to the

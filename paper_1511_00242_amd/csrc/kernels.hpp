@@ -330,8 +330,13 @@ __device__ __forceinline__ void dfeq_pair_unweighted(int A, const Mom<T> &m, T q
     const T em = REF ? edot<T>(A, m.mx, m.my) : eM;
     const T q = A == 0 ? -m.msq15 : fma((T)4.5 * eM, eM, -m.msq15);
     const T s = fma(m.inv, q, REF ? m.drho - q0 : m.drho);
-    Qa = A == 0 ? s : fma((T)3, em, s);
-    Qr = A == 0 ? s : fma((T)-3, em, s);
+    // FP64: 3 held in a scalar register pair.  As a literal it can only be the operand of
+    // the two-operand fused multiply-add, which overwrites its addend, so s would be copied
+    // first for the second direction of the pair (one 64-bit move per pair).
+    T three = (T)3;
+    if constexpr (sizeof(T) == 8) asm("" : "+s"(three));
+    Qa = A == 0 ? s : fma(three, em, s);
+    Qr = A == 0 ? s : fma(-three, em, s);
 }
 // dfeq - x from the unweighted deviation Q.  FP64 folds the weight into one fused
 // multiply-add (one rounding).  FP32 keeps the two-term weight: hi Q - x first, in one

@@ -264,6 +264,8 @@ def test_nonfinite_value_gives_unstable(compute, storage, direction, bad):
         f[direction, 5, 67] = bad
         ctx.set_f(f)
         ctx.dugks_step(1)                       # the check after this step sees it
+        import torch
+        torch.cuda.synchronize()                # checks are read without waiting: let it finish
         with pytest.raises(L.LbfvError) as e:
             ctx.dugks_step(1)
         assert e.value.status == L.LBFV_EUNSTABLE
