@@ -26,7 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-HEADLINE_TILE = (110, 1)        # rows per block, waves per block of the timed 4096^2 step, and
+HEADLINE_TILE = (205, 1)        # rows per block, waves per block of the timed 4096^2 step, and
 HEADLINE_TIME_BLOCK = 4        # steps per launch (fixed so that the committed counter profile
                                # describes the same launches)
 HEADLINE_PAIRS = 0             # two steps per launch: one wave (0) or a pair of waves (1) per item
@@ -664,6 +664,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": traffic_gbs,
                      "traffic_bytes_per_launch": traffic_bytes,
+                     "traffic_frac": traffic_gbs / HBM_PEAK_GBS if traffic_gbs else None,
+                     "limiter": ("vector ALU and power: the state crosses HBM once per launch of "
+                                 f"{head['time_block']} steps" if head["time_block"] > 1 else "HBM"),
                      "kernel": (f"lbfv::stepc_kernel<double,double,DUGKS,{head['time_block']}>" if head["time_block"] >= 3
                                 else ("lbfv::step2p_kernel<double,double,DUGKS>" if head["wave_pairs"]
                                       else "lbfv::step2_kernel<double,double,DUGKS>") if head["time_block"] == 2

@@ -43,7 +43,7 @@ import make_long_horizon as G   # noqa: E402
 pytestmark = pytest.mark.gpu
 TOL64 = 1e-12
 TOL32_U = 1e-5
-BENCH_TILE = (110, 1)            # the timed 4096^2 launch shape: rows, waves per block,
+BENCH_TILE = (205, 1)            # the timed 4096^2 launch shape: rows, waves per block,
 BENCH_TB = 4                    # four steps per launch (a chain of four waves per work item),
 BENCH_PAIRS = False             # the pair form's switch (it applies to two steps per launch)
 THREADS = min(16, int(os.environ.get("LBFV_ORACLE_THREADS", os.environ.get("OMP_NUM_THREADS", "8"))))
