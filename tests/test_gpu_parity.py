@@ -274,6 +274,25 @@ def test_nonfinite_value_gives_unstable(compute, storage, direction, bad):
         assert e.value.status == L.LBFV_EUNSTABLE
 
 
+@pytest.mark.parametrize("tb", [2, 3, 4])
+def test_nonfinite_check_after_launches_of_several_steps(tb):
+    # the check falls due at 5 steps and runs at the end of the launch that crosses it; 7 steps
+    # at 3 or 4 per launch end with a shorter launch, after which the check still runs
+    w = I.taylor_green(64)
+    with L.Context(w.xf, w.yf, w.tau, w.dt, bcs=w.bcs, check_every=5) as ctx:
+        ctx.init_equilibrium(w.rho, w.ux, w.uy)
+        ctx.set_time_block(tb)
+        f = ctx.get_f()
+        f[6, 40, 13] = np.nan
+        ctx.set_f(f)
+        ctx.dugks_step(7)
+        import torch
+        torch.cuda.synchronize()
+        with pytest.raises(L.LbfvError) as e:
+            ctx.dugks_step(1)
+        assert e.value.status == L.LBFV_EUNSTABLE
+
+
 def test_graph_replay_equals_single_launches_and_is_deterministic():
     w = _mixed_workload(70, 33)
     ora = oracle_case(w)
