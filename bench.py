@@ -6,10 +6,11 @@ the 256 MB Infinity Cache, so that HBM bandwidth is what is measured).  One
 "step" is one full time step of the path (moments, equilibrium and collision
 transforms, reconstruction and half-step trace at every face, wall / ghost
 handling, interface moments and back-transform, flux divergence and update),
-with the FP64 check reduction (totals + non-finite flag) every `--check-every`
-steps inside the timed region.  Inputs are resident in HBM before timing starts.
+with the library's non-finite check every `--check-every` steps inside the timed
+region.  Inputs are resident in HBM before timing starts.
 
-Prints one JSON line (rank 0); see the design doc for the fields.
+Prints one JSON line (rank 0): the metric and its value, the roofline of the timed kernel
+(algorithmic and measured bytes), the variants and the CPU baseline.
 """
 from __future__ import annotations
 

@@ -14,8 +14,8 @@
  * OpenMP only splits independent rows of a stage, so results do not depend on
  * the thread count.  Reductions run serially in a fixed order.
  *
- * Readings of passages the paper leaves open (each is documented again in
- * the design doc under the same tag):
+ * Readings of passages the paper leaves open (the tag names the same reading
+ * wherever it is cited):
  *   R1 flux sign: outward normals; update = psi - dt/|V| * sum (xi.n_out) f_b S
  *      (the explicit minus of the structured-mesh form, Sec. 2.3, Eq. bkg_fv).
  *   R2 linear reconstruction of the half-step characteristic value for BOTH
