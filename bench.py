@@ -33,6 +33,8 @@ HEADLINE_TIME_BLOCK = 4        # steps per launch (fixed so that the committed c
 HEADLINE_PAIRS = 0             # two steps per launch: one wave (0) or a pair of waves (1) per item
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_dugks_fp64_taylor_green_4096.txt")
 BYTES = {"f64": 144, "f32": 72, "bf16": 36, "f16": 36}   # algorithmic bytes per cell-step (9 reads + 9 writes)
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X: 256 CUs x 4 SIMDs x 16 FP64 lanes x 2 (FMA) x 2.4 GHz
+DUGKS_FLOP_PER_CELL_STEP = 600  # algorithmic FP operations of one DUGKS cell update (each face once)
 
 
 def parse():
@@ -674,6 +676,11 @@ def main():
                                 else "lbfv::step_kernel<double,double,DUGKS>"),
                      "steps_per_launch": head["time_block"],
                      "kernel_ms": kern["ms_per_step"],
+                     "alu": {"achieved": cells * DUGKS_FLOP_PER_CELL_STEP / (kern["ms_per_step"] * 1e-3) / 1e12,
+                             "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": cells * DUGKS_FLOP_PER_CELL_STEP / (kern["ms_per_step"] * 1e-3) / 1e12
+                             / FP64_VECTOR_PEAK_TFLOPS,
+                             "flop_per_cell_step": DUGKS_FLOP_PER_CELL_STEP},
                      "bytes_per_cell_step": BYTES["f64"]},
         "burn_in": head.get("burn_in"),
         "variants": variants,
