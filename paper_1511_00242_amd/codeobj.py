@@ -62,7 +62,19 @@ def kernel_isa_sha256(lib: str, kernel: str) -> str | None:
     elf = extract(lib)
     if elf is None:
         return None
+    return _digest(elf, symbols(elf), kernel)
+
+
+def kernel_digests(lib: str) -> dict | None:
+    """kernel_isa_sha256 of every kernel in `lib`, from one extraction: {mangled name: digest}."""
+    elf = extract(lib)
+    if elf is None:
+        return None
     syms = symbols(elf)
+    return {k: _digest(elf, syms, k) for k in syms if not k.endswith(".kd") and k + ".kd" in syms}
+
+
+def _digest(elf: bytes, syms: dict, kernel: str) -> str | None:
     if kernel not in syms or kernel + ".kd" not in syms:
         return None
     h = hashlib.sha256()

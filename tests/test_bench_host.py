@@ -44,3 +44,18 @@ def test_traffic_withheld_for_another_kernel(monkeypatch):
     monkeypatch.setattr(bench, "HEADLINE_KERNEL", other)
     assert bench.profiled_traffic(bench.HEADLINE_TILE, bench.HEADLINE_TIME_BLOCK, 0.25,
                                   bench.HEADLINE_PAIRS) == (None, None)
+
+
+def test_every_counter_profile_describes_a_built_kernel():
+    # each committed rocprofv3 summary names the machine-code digest of the kernel it measured;
+    # all of them must still be kernels of the built library
+    import re
+    _need_digest()
+    built = set(codeobj.kernel_digests(L._LIB_PATH).values())
+    pdir = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles")
+    seen = 0
+    for name in sorted(os.listdir(pdir)):
+        for h in set(re.findall(r"\b[0-9a-f]{64}\b", open(os.path.join(pdir, name)).read())):
+            seen += 1
+            assert h in built, f"{name}: profiled kernel {h[:12]} is not in the built library"
+    assert seen >= 5
